@@ -434,7 +434,8 @@ int oracle_adjoint(const oracle_grid *g, const double *m, const double *eta,
         if (nrec > 0) inject(&R, nc, dt2, dres + (int64_t)k * nrec, C.a, v_m);
         real *t = v_p; v_p = v_c; v_c = v_m; v_m = t;
     }
-    if (v_final) for (int64_t p = 0; p < N; ++p) v_final[p] = (double)v_c[p];
+    /* after the k = 0 update v_p holds v^0, the last state sampled */
+    if (v_final) for (int64_t p = 0; p < N; ++p) v_final[p] = (double)v_p[p];
 out:
     free(v_p); free(v_c); free(v_m);
     free_coef(&C);

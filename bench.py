@@ -1,0 +1,132 @@
+"""Throughput of the damped-acoustic forward propagator on one MI355X.
+
+One bench step = one full forward modelling run of the workload (every time
+step: stencil + leapfrog + damping, fused source injection and receiver
+sampling), inputs resident in HBM.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Workloads (seeded synthetic layered models, sponge, Ricker source):
+  3d-256-o8   256^3, space order 8, 1000 steps, 128x128 receivers (default)
+  3d-512-o16  512^3, space order 16, 2000 steps, 256x256 receivers
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gpts/s (grid-point updates/sec) + % HBM roofline; FWI gradient sec/shot vs plain"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = 20     # read u^n, u^{n-1}, alpha, beta; write u^{n+1} (FP32)
+
+
+def make_workload(name):
+    from paper_1609_03361_amd import synth
+    if name == "3d-256-o8":
+        return synth.config_3d_o8()
+    if name == "3d-512-o16":
+        return synth.config_3d_o16()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(p, steps):
+    """The FP64 oracle on the host cores, on the first `steps` time steps of
+    the same workload (full grid)."""
+    import oracle
+    t0 = time.perf_counter()
+    oracle.forward(p.shape, p.spacing, p.order, p.dt, steps, p.m, p.eta, p.src,
+                   p.q[:steps], p.rec, want_final=False)
+    el = time.perf_counter() - t0
+    return {"value": p.npoints * steps / el / 1e9, "unit": "Gpts/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{'x'.join(map(str, p.shape))} grid, order {p.order}, first {steps} of "
+                      f"{p.nt} time steps, FP64, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="3d-256-o8")
+    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build runs on a single MI355X and has no "
+              f"multi-GPU path (asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1609_03361_amd import api, _lib
+
+    dev = torch.device("cuda:0")
+    p = make_workload(args.workload)
+    geom = api.Geometry(p.shape, p.spacing, p.order, p.dt, p.nt, p.src, p.rec)
+    m = torch.from_numpy(p.m).to(dev)
+    eta = torch.from_numpy(p.eta).to(dev)
+    q = torch.from_numpy(p.q).to(dev)
+    print(f"# workload {p.name}: shape {p.shape} order {p.order} nt {p.nt} "
+          f"nrec {p.rec.shape[0]}", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        api.forward(geom, m, eta, q)
+    torch.cuda.synchronize()
+
+    _lib.set_profiling(True)
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    loop_ms, launches = 0.0, 0
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        api.forward(geom, m, eta, q)
+        ms, n = _lib.last_loop()          # waits for this run's loop to end
+        loop_ms += ms
+        launches += n
+    e1.record(stream)
+    torch.cuda.synchronize()
+    _lib.set_profiling(False)
+    total_ms = e0.elapsed_time(e1)
+
+    updates = p.npoints * p.nt * args.steps
+    value = updates / (total_ms * 1e-3) / 1e9
+    per_launch_ms = loop_ms / launches
+    alg_bytes = BYTES_PER_UPDATE * p.npoints
+    achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total_ms / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": p.name, "shape": list(p.shape), "space_order": p.order,
+                   "time_steps": p.nt, "receivers": int(p.rec.shape[0]), "sources": 1,
+                   "bench_step": "one full forward modelling run"},
+        "hbm_roofline_frac": round(value * BYTES_PER_UPDATE / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "leapfrog step", "launch_ms": round(per_launch_ms, 5),
+                     "alg_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

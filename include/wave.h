@@ -1,0 +1,189 @@
+/*
+ * wave.h — C ABI of the MI355X damped-acoustic finite-difference propagator.
+ *
+ * The method is the explicit scheme of the paper's seismic-inversion example
+ * (Section "Seismic Inversion Example", equation "eqn:acoustic"):
+ *
+ *     m u_tt + eta u_t - lap(u) = q
+ *
+ * second order in time (central differences for u_tt and u_t), order 2..16
+ * in space (Section "High-level API": u.laplace is the sum over axes of the
+ * order-2k central second derivative), solved for the next time level as in
+ * the forward listing ("lst:wave"):
+ *
+ *     u^{n+1} = (2 m u^n - (m - eta dt/2) u^{n-1} + dt^2 L u^n) / (m + eta dt/2)
+ *
+ * Sources are injected and receivers sampled by multilinear interpolation
+ * over the 2^d nodes of the enclosing cell (Section "Sparse point
+ * interpolation"): step n samples d^n from u^n and adds
+ * dt^2 q^n w / (m + eta dt/2) to u^{n+1}.  Outside the grid the field is
+ * zero.  The adjoint ("lst:adjoint") runs the same update backwards in time
+ * with the roles of sources and receivers exchanged.
+ *
+ * Conventions for every entry point
+ *   - Layout: C-contiguous, depth z fastest.  2D fields are [nx][nz], 3D
+ *     fields [nx][ny][nz]; traces and wavelets are time-major [nt][npts].
+ *   - Field, trace, wavelet, gradient and workspace pointers are DEVICE
+ *     pointers (FP32 unless stated).  Coordinates are HOST FP64 [npts][ndim],
+ *     metres from grid index 0, and are copied during the call.
+ *   - The caller owns every buffer, including the workspace; the library
+ *     allocates no device memory.  Buffers must not overlap unless stated.
+ *   - Validation is synchronous and happens before any write to an output:
+ *     on a non-zero return no output has been touched.  Validation reads
+ *     m and eta on `stream` and waits for it once per call.  After that the
+ *     work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
+ *     and the call returns; faults surface at the caller's next synchronise.
+ *   - Return codes are the wave_status values below; wave_last_error() gives
+ *     a thread-local message for the last non-zero return.  Nothing throws
+ *     or aborts across this interface.
+ *   - Calls that share a workspace must be ordered on one stream.
+ */
+#ifndef WAVE_H
+#define WAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WAVE_OK = 0,
+    WAVE_EINVAL = -1,     /* bad argument: null pointer, ndim, order, nt, shape, dt, fields */
+    WAVE_ECFL = -2,       /* dt above the stability bound of the scheme */
+    WAVE_ERANGE = -3,     /* a sparse point lies outside [0, (n_a - 1) h_a] on some axis */
+    WAVE_EWORKSPACE = -4, /* workspace missing, misaligned or too small */
+    WAVE_EHIP = -5        /* the HIP runtime reported an error */
+} wave_status;
+
+/* Grid and time axis.  Section "High-level API" (space_order on the symbol,
+ * u.laplace) and the listings' problem statement forward(model, nt, dt, h,
+ * order).  2D: shape = {nx, nz, 0}, spacing = {hx, hz, 0}. */
+typedef struct {
+    int32_t ndim;          /* 2 or 3 */
+    int32_t space_order;   /* 2, 4, ..., 16 */
+    int64_t shape[3];      /* points per axis, each >= 2 */
+    double spacing[3];     /* metres, > 0 */
+    double dt;             /* seconds, > 0 */
+    int32_t nt;            /* time steps, >= 1 */
+    int32_t reserved;      /* set to 0 */
+} wave_grid;
+
+/* Sparse points (Section "Sparse point interpolation"). */
+typedef struct {
+    int32_t npts;          /* >= 0 */
+    int32_t reserved;      /* set to 0 */
+    const double* coords;  /* HOST [npts][ndim], metres; may be NULL when npts == 0 */
+} wave_points;
+
+typedef enum { WAVE_CKPT_FP32 = 0, WAVE_CKPT_BF16 = 1, WAVE_CKPT_FP16 = 2 } wave_ckpt_dtype;
+
+/* Per-call options.  A zero-initialised struct plus a workspace is valid. */
+typedef struct {
+    void* workspace;          /* DEVICE, 256-byte aligned, >= wave_workspace_size() bytes */
+    size_t workspace_bytes;
+    int32_t ckpt_every;       /* gradient/checkpointing: steps per segment, 0 = 20 */
+    int32_t ckpt_dtype;       /* wave_ckpt_dtype for stored snapshots */
+    int32_t tile;             /* 0 = automatic, > 0 = explicit kernel tile id */
+    int32_t flags;            /* reserved, set to 0 */
+} wave_opts;
+
+typedef enum {
+    WAVE_OP_FORWARD = 0,      /* wave_forward (no checkpoints) */
+    WAVE_OP_ADJOINT = 1,      /* wave_adjoint */
+    WAVE_OP_GRADIENT = 2,     /* wave_gradient, wave_backward, wave_forward with checkpoints */
+} wave_op;
+
+/* Bytes of workspace an entry point needs for this grid and point sets
+ * (checkpoint storage is separate: wave_checkpoint_size).  Returns a
+ * wave_status; *bytes is written on success. */
+int wave_workspace_size(int32_t op, const wave_grid* grid, const wave_points* src,
+                        const wave_points* rec, const wave_opts* opts, size_t* bytes);
+
+/* Bytes of checkpoint storage for opts->ckpt_every / opts->ckpt_dtype:
+ * one (u^c, u^{c-1}) pair per segment, plus one FP32 scale per snapshot. */
+int wave_checkpoint_size(const wave_grid* grid, const wave_opts* opts, size_t* bytes);
+
+/*
+ * Forward modelling (listing "lst:wave" plus point-to-grid injection and
+ * grid-to-point sampling).
+ *   m      [shape]  squared slowness 1/v^2 (s^2/m^2), finite, > 0
+ *   eta    [shape]  damping (s/m^2), finite, >= 0; NULL means eta = 0
+ *   src, q          source positions and wavelets q [nt][nsrc]
+ *   rec, d          receiver positions and traces d [nt][nrec] (written; d^n from u^n)
+ *   u_final         NULL or [shape]: receives u^nt
+ *   ckpt            NULL, or checkpoint storage of wave_checkpoint_size()
+ *                   bytes: receives the (u^c, u^{c-1}) pairs that
+ *                   wave_backward replays
+ */
+int wave_forward(const wave_grid* grid, const float* m, const float* eta,
+                 const wave_points* src, const float* q,
+                 const wave_points* rec, float* d,
+                 float* u_final, void* ckpt, const wave_opts* opts, void* stream);
+
+/*
+ * Adjoint modelling (listing "lst:adjoint": the eta term enters with the
+ * opposite sign and the update is solved for the backward level).  Driven by
+ * receiver data, sampled at the sources; it is the exact transpose of the
+ * map q -> d of wave_forward:
+ *   for k = nt-1 .. 0:  q_adj^k = sample of v^k at the sources,
+ *                       v^{k-1} = update(v^k, v^{k+1}) + dt^2 d^k w / (m + eta dt/2)
+ *   d      [nt][nrec]  adjoint source
+ *   q_adj  [nt][nsrc]  written
+ *   v_final NULL or [shape]: receives v^0
+ */
+int wave_adjoint(const wave_grid* grid, const float* m, const float* eta,
+                 const wave_points* rec, const float* d,
+                 const wave_points* src, float* q_adj,
+                 float* v_final, const wave_opts* opts, void* stream);
+
+/*
+ * Adjoint-state backward pass from stored checkpoints.  For the data map
+ * d = F(m, q) of wave_forward and an adjoint source r = dJ/dd [nt][nrec]:
+ *   grad_m [shape]      written: dJ/dm = -sum_n v^n (u^{n+1} - 2u^n + u^{n-1}) / dt^2
+ *                       with v the adjoint field driven by r (eta held fixed)
+ *   grad_q [nt][nsrc]   NULL or written: dJ/dq (the adjoint sampled at the sources)
+ * `ckpt` must come from wave_forward with the same grid, fields, sources,
+ * wavelets and opts->ckpt_every/ckpt_dtype.
+ */
+int wave_backward(const wave_grid* grid, const float* m, const float* eta,
+                  const wave_points* src, const float* q,
+                  const wave_points* rec, const float* r,
+                  const void* ckpt, float* grad_m, float* grad_q,
+                  const wave_opts* opts, void* stream);
+
+/*
+ * Misfit and gradient for one shot (the gradient test of Section
+ * "Performance" of the seismic example): forward with checkpoints, residual
+ * r = d - d_obs, J = 1/2 sum r^2, then wave_backward(r).
+ *   d_obs  [nt][nrec]
+ *   grad   [shape]   written, dJ/dm
+ *   misfit DEVICE    one float, written: J
+ *   d_syn  NULL or [nt][nrec]: receives the modelled data
+ * The workspace (op WAVE_OP_GRADIENT) includes the checkpoint storage.
+ */
+int wave_gradient(const wave_grid* grid, const float* m, const float* eta,
+                  const wave_points* src, const float* q,
+                  const wave_points* rec, const float* d_obs,
+                  float* grad, float* misfit, float* d_syn,
+                  const wave_opts* opts, void* stream);
+
+/* Phase timing (a metrics aid).  With profiling on, each entry point called
+ * by this thread records HIP events on its stream around its time loop(s),
+ * from the first step launch to the last (set-up excluded).
+ * wave_last_loop waits for the last call's end event and reports the
+ * elapsed milliseconds and the number of step launches it made. */
+int wave_set_profiling(int32_t enable);
+int wave_last_loop(double* ms, int64_t* launches);
+
+/* Thread-local message describing the last non-zero return ("" if none). */
+const char* wave_last_error(void);
+
+/* Library version string. */
+const char* wave_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WAVE_H */

@@ -1,0 +1,187 @@
+"""PyTorch-facing wrappers over the C ABI (device memory and streams only).
+
+Every step of the method runs inside libwave.so; these functions allocate
+the caller-owned buffers (outputs, workspace, checkpoints) as torch tensors
+and pass raw pointers plus the current HIP stream.
+
+Arguments mirror the paper's problem statement forward(model, nt, dt, h,
+order): ``m`` and ``eta`` are FP32 device tensors of the grid's shape (z
+fastest), ``spacing`` the grid spacing per axis in metres, ``src``/``rec``
+host FP64 coordinates ``[n][ndim]`` in metres, ``q`` the source wavelets
+``[nt][nsrc]`` (FP32, device).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+__all__ = ["Geometry", "forward", "adjoint", "backward", "gradient", "checkpoint_bytes",
+           "WaveFn", "wave_apply"]
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _need(t, name, shape=None):
+    if t is None:
+        return
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 device tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _stream(dev):
+    return C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _workspace(op, grid, sp, rp, opts_kw, dev):
+    nbytes = C.c_size_t(0)
+    o = L.make_opts(**opts_kw)
+    L.check(L.lib().wave_workspace_size(op, C.byref(grid), C.byref(sp.s), C.byref(rp.s),
+                                        C.byref(o), C.byref(nbytes)), "wave_workspace_size")
+    buf = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
+    base = buf.data_ptr()
+    off = (-base) % 256
+    o = L.make_opts(base + off, int(nbytes.value), **opts_kw)
+    return buf, o
+
+
+@dataclass
+class Geometry:
+    """Grid, time axis and sparse-point positions of one shot."""
+    shape: tuple
+    spacing: tuple
+    order: int
+    dt: float
+    nt: int
+    src: object = None     # host FP64 [nsrc][ndim]
+    rec: object = None     # host FP64 [nrec][ndim]
+
+    def grid(self):
+        return L.make_grid(self.shape, self.spacing, self.order, self.dt, self.nt)
+
+    def points(self):
+        nd = len(self.shape)
+        return L.HostPoints(self.src, nd), L.HostPoints(self.rec, nd)
+
+
+def checkpoint_bytes(geom: Geometry, ckpt_every=0, ckpt_dtype="fp32") -> int:
+    n = C.c_size_t(0)
+    o = L.make_opts(ckpt_every=ckpt_every, ckpt_dtype=ckpt_dtype)
+    L.check(L.lib().wave_checkpoint_size(C.byref(geom.grid()), C.byref(o), C.byref(n)),
+            "wave_checkpoint_size")
+    return int(n.value)
+
+
+def forward(geom: Geometry, m, eta=None, q=None, return_final=False, checkpoint=None,
+            ckpt_every=0, ckpt_dtype="fp32", tile=0):
+    """Modelled traces d [nt][nrec] (and u^nt if ``return_final``).
+    ``checkpoint``: optional uint8 device tensor of checkpoint_bytes() that
+    receives the snapshots wave_backward replays."""
+    _need(m, "m", geom.shape)
+    _need(eta, "eta", geom.shape)
+    sp, rp = geom.points()
+    if sp.npts:
+        _need(q, "q", (geom.nt, sp.npts))
+    dev = m.device
+    grid = geom.grid()
+    kw = dict(ckpt_every=ckpt_every, ckpt_dtype=ckpt_dtype, tile=tile)
+    op = L.WAVE_OP_GRADIENT if checkpoint is not None else L.WAVE_OP_FORWARD
+    ws, o = _workspace(op, grid, sp, rp, kw, dev)
+    d = torch.empty((geom.nt, rp.npts), dtype=torch.float32, device=dev)
+    uf = torch.empty(geom.shape, dtype=torch.float32, device=dev) if return_final else None
+    L.check(L.lib().wave_forward(C.byref(grid), _ptr(m), _ptr(eta), C.byref(sp.s), _ptr(q),
+                                 C.byref(rp.s), _ptr(d) if rp.npts else None, _ptr(uf),
+                                 _ptr(checkpoint), C.byref(o), _stream(dev)), "wave_forward")
+    return (d, uf) if return_final else d
+
+
+def adjoint(geom: Geometry, m, eta, d, return_final=False, tile=0):
+    """Adjoint modelling: receiver data d [nt][nrec] -> q_adj [nt][nsrc] (and v^0)."""
+    _need(m, "m", geom.shape)
+    _need(eta, "eta", geom.shape)
+    sp, rp = geom.points()
+    _need(d, "d", (geom.nt, rp.npts))
+    dev = m.device
+    grid = geom.grid()
+    ws, o = _workspace(L.WAVE_OP_ADJOINT, grid, sp, rp, dict(tile=tile), dev)
+    qa = torch.empty((geom.nt, sp.npts), dtype=torch.float32, device=dev)
+    vf = torch.empty(geom.shape, dtype=torch.float32, device=dev) if return_final else None
+    L.check(L.lib().wave_adjoint(C.byref(grid), _ptr(m), _ptr(eta), C.byref(rp.s), _ptr(d),
+                                 C.byref(sp.s), _ptr(qa) if sp.npts else None, _ptr(vf),
+                                 C.byref(o), _stream(dev)), "wave_adjoint")
+    return (qa, vf) if return_final else qa
+
+
+def backward(geom: Geometry, m, eta, q, r, checkpoint, ckpt_every=0, ckpt_dtype="fp32",
+             want_grad_q=True, tile=0):
+    """dJ/dm (and dJ/dq) for the adjoint source r = dJ/dd, replaying ``checkpoint``."""
+    _need(m, "m", geom.shape)
+    _need(eta, "eta", geom.shape)
+    sp, rp = geom.points()
+    _need(r, "r", (geom.nt, rp.npts))
+    dev = m.device
+    grid = geom.grid()
+    kw = dict(ckpt_every=ckpt_every, ckpt_dtype=ckpt_dtype, tile=tile)
+    ws, o = _workspace(L.WAVE_OP_GRADIENT, grid, sp, rp, kw, dev)
+    g = torch.empty(geom.shape, dtype=torch.float32, device=dev)
+    gq = torch.empty((geom.nt, sp.npts), dtype=torch.float32, device=dev) \
+        if (want_grad_q and sp.npts) else None
+    L.check(L.lib().wave_backward(C.byref(grid), _ptr(m), _ptr(eta), C.byref(sp.s), _ptr(q),
+                                  C.byref(rp.s), _ptr(r), _ptr(checkpoint), _ptr(g), _ptr(gq),
+                                  C.byref(o), _stream(dev)), "wave_backward")
+    return g, gq
+
+
+def gradient(geom: Geometry, m, eta, q, d_obs, ckpt_every=0, ckpt_dtype="fp32",
+             return_data=False, tile=0):
+    """Misfit J = 1/2 ||d - d_obs||^2 (device scalar) and dJ/dm for one shot."""
+    _need(m, "m", geom.shape)
+    _need(eta, "eta", geom.shape)
+    sp, rp = geom.points()
+    _need(d_obs, "d_obs", (geom.nt, rp.npts))
+    dev = m.device
+    grid = geom.grid()
+    kw = dict(ckpt_every=ckpt_every, ckpt_dtype=ckpt_dtype, tile=tile)
+    ws, o = _workspace(L.WAVE_OP_GRADIENT, grid, sp, rp, kw, dev)
+    g = torch.empty(geom.shape, dtype=torch.float32, device=dev)
+    J = torch.empty((), dtype=torch.float32, device=dev)
+    dsyn = torch.empty((geom.nt, rp.npts), dtype=torch.float32, device=dev) if return_data else None
+    L.check(L.lib().wave_gradient(C.byref(grid), _ptr(m), _ptr(eta), C.byref(sp.s), _ptr(q),
+                                  C.byref(rp.s), _ptr(d_obs), _ptr(g), _ptr(J), _ptr(dsyn),
+                                  C.byref(o), _stream(dev)), "wave_gradient")
+    return (J, g, dsyn) if return_data else (J, g)
+
+
+class WaveFn(torch.autograd.Function):
+    """d = F(m, q): forward modelling with checkpointed snapshots; the backward
+    is the hand-written adjoint with the imaging condition (wave_backward)."""
+
+    @staticmethod
+    def forward(ctx, m, q, eta, geom, ckpt_every=0, ckpt_dtype="fp32"):
+        ck = torch.empty(checkpoint_bytes(geom, ckpt_every, ckpt_dtype), dtype=torch.uint8,
+                         device=m.device)
+        d = forward(geom, m.detach(), None if eta is None else eta.detach(), q.detach(),
+                    checkpoint=ck, ckpt_every=ckpt_every, ckpt_dtype=ckpt_dtype)
+        ctx.save_for_backward(m, q, eta, ck)
+        ctx.geom, ctx.ck_every, ctx.ck_dtype = geom, ckpt_every, ckpt_dtype
+        return d
+
+    @staticmethod
+    def backward(ctx, grad_d):
+        m, q, eta, ck = ctx.saved_tensors
+        g, gq = backward(ctx.geom, m.detach(), None if eta is None else eta.detach(), q.detach(),
+                         grad_d.detach().contiguous().float(), ck, ctx.ck_every, ctx.ck_dtype,
+                         want_grad_q=ctx.needs_input_grad[1])
+        return g, gq, None, None, None, None
+
+
+def wave_apply(geom: Geometry, m, q, eta=None, ckpt_every=0, ckpt_dtype="fp32"):
+    """Differentiable forward modelling: traces as a function of (m, q)."""
+    return WaveFn.apply(m, q, eta, geom, ckpt_every, ckpt_dtype)

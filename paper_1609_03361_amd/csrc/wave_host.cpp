@@ -1,0 +1,745 @@
+// Host side of the C ABI declared in include/wave.h: argument validation,
+// finite-difference weights, stability bound, sparse-point tables, workspace
+// layout and the time loops that enqueue the gfx950 kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <string>
+#include <vector>
+
+#include "../../include/wave.h"
+#include "wave_internal.h"
+
+using namespace wave;
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(WAVE_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                          \
+    } while (0)
+
+// Optional per-thread phase timing (wave_set_profiling / wave_last_loop).
+struct Prof {
+    bool on = false;
+    bool have = false;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    int64_t launches = 0;
+};
+thread_local Prof g_prof;
+
+int prof_begin(hipStream_t s)
+{
+    g_prof.launches = 0;
+    g_prof.have = false;
+    if (!g_prof.on) return 0;
+    if (!g_prof.t0 && hipEventCreate(&g_prof.t0) != hipSuccess) return -1;
+    if (!g_prof.t1 && hipEventCreate(&g_prof.t1) != hipSuccess) return -1;
+    return hipEventRecord(g_prof.t0, s) == hipSuccess ? 0 : -1;
+}
+
+int prof_end(hipStream_t s)
+{
+    if (!g_prof.on) return 0;
+    if (hipEventRecord(g_prof.t1, s) != hipSuccess) return -1;
+    g_prof.have = true;
+    return 0;
+}
+
+constexpr size_t kAlign = 256;
+constexpr int kCheckBlocks = 512;
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// Grid description
+// ---------------------------------------------------------------------------
+struct Geo {
+    int ndim = 0, order = 0, half = 0, nt = 0;
+    int64_t n[3] = {0, 0, 0};     // 3D view: (nx, ny, nz); 2D: (nx, 1, nz)
+    double h[3] = {0, 0, 0};      // spacing in the 3D view (2D: hy unused)
+    double dt = 0;
+    int64_t npts() const { return n[0] * n[1] * n[2]; }
+    int64_t nrows() const { return n[0] * n[1]; }
+};
+
+int make_geo(const wave_grid* g, Geo* G)
+{
+    if (!g) return fail(WAVE_EINVAL, "grid is NULL");
+    if (g->ndim != 2 && g->ndim != 3) return fail(WAVE_EINVAL, "ndim must be 2 or 3 (got %d)", g->ndim);
+    if (g->space_order < 2 || g->space_order > 16 || (g->space_order & 1))
+        return fail(WAVE_EINVAL, "space_order must be even in [2, 16] (got %d)", g->space_order);
+    if (g->nt < 1) return fail(WAVE_EINVAL, "nt must be >= 1 (got %d)", g->nt);
+    if (!(g->dt > 0.0) || !std::isfinite(g->dt)) return fail(WAVE_EINVAL, "dt must be finite and > 0");
+    for (int a = 0; a < g->ndim; ++a) {
+        if (g->shape[a] < 2) return fail(WAVE_EINVAL, "shape[%d] must be >= 2", a);
+        if (g->shape[a] > (int64_t)1 << 31) return fail(WAVE_EINVAL, "shape[%d] too large", a);
+        if (!(g->spacing[a] > 0.0) || !std::isfinite(g->spacing[a]))
+            return fail(WAVE_EINVAL, "spacing[%d] must be finite and > 0", a);
+    }
+    G->ndim = g->ndim;
+    G->order = g->space_order;
+    G->half = g->space_order / 2;
+    G->nt = g->nt;
+    G->dt = g->dt;
+    if (g->ndim == 3) {
+        for (int a = 0; a < 3; ++a) { G->n[a] = g->shape[a]; G->h[a] = g->spacing[a]; }
+    } else {
+        G->n[0] = g->shape[0]; G->n[1] = 1; G->n[2] = g->shape[1];
+        G->h[0] = g->spacing[0]; G->h[1] = 1.0; G->h[2] = g->spacing[1];
+    }
+    const double total = (double)G->n[0] * (double)G->n[1] * (double)G->n[2];
+    if (total > 4.0e10) return fail(WAVE_EINVAL, "grid has too many points");
+    if ((double)G->n[0] * (double)G->n[1] >= 2147483647.0)
+        return fail(WAVE_EINVAL, "nx * ny must be below 2^31");
+    return WAVE_OK;
+}
+
+// Central second-derivative weights of order 2k (Section "High-level API":
+// f.dx2 with space_order = 2k), closed form
+//   c_j = 2 (-1)^(j+1) (k!)^2 / (j^2 (k-j)! (k+j)!),  j = 1..k,
+// evaluated as an exact integer ratio in double (every factor < 2^53 for
+// k <= 8), so each c_j is the correctly rounded value.
+void fd_weights(int k, double* c)
+{
+    auto fact = [](int v) { double f = 1; for (int i = 2; i <= v; ++i) f *= i; return f; };
+    const double kf = fact(k);
+    for (int j = 1; j <= k; ++j) {
+        const double num = 2.0 * kf * kf;
+        const double den = (double)j * j * fact(k - j) * fact(k + j);
+        c[j] = ((j & 1) ? 1.0 : -1.0) * (num / den);
+    }
+    double s = 0;
+    for (int j = 1; j <= k; ++j) s += c[j];
+    c[0] = -2.0 * s;
+}
+
+// Leapfrog stability (eta = 0; damping does not tighten it): the largest
+// eigenvalue of -L is at most sum_a S/h_a^2 with S = sum_j |c_j| over the full
+// stencil, and the scheme is stable when vmax^2 dt^2 max|lambda| <= 4.
+double cfl_dt_max(const Geo& G, double vmax)
+{
+    double c[kMaxHalf + 1];
+    fd_weights(G.half, c);
+    double S = std::fabs(c[0]);
+    for (int j = 1; j <= G.half; ++j) S += 2.0 * std::fabs(c[j]);
+    double lam = 0;
+    for (int a = 0; a < 3; ++a)
+        if (G.ndim == 3 || a != 1) lam += S / (G.h[a] * G.h[a]);
+    return 2.0 / (vmax * std::sqrt(lam));
+}
+
+// ---------------------------------------------------------------------------
+// Sparse points: multilinear weights over the enclosing cell.
+// ---------------------------------------------------------------------------
+struct HostPoints {
+    int npts = 0;
+    std::vector<int64_t> base;     // flat index of the cell's lowest corner
+    std::vector<float> w;          // [npts][2^d]
+    std::vector<int64_t> cell;     // [npts][3] lowest-corner index per 3D-view axis
+};
+
+int make_points(const Geo& G, const wave_points* P, const char* what, HostPoints* out)
+{
+    out->npts = 0;
+    if (!P || P->npts == 0) return WAVE_OK;
+    if (P->npts < 0) return fail(WAVE_EINVAL, "%s: npts < 0", what);
+    if (!P->coords) return fail(WAVE_EINVAL, "%s: coords is NULL", what);
+    const int d = G.ndim, nc = 1 << d;
+    const int np = P->npts;
+    out->npts = np;
+    out->base.resize(np);
+    out->w.resize((size_t)np * nc);
+    out->cell.resize((size_t)np * 3);
+    // the caller's axes map onto the 3D view: 3D (x,y,z) -> 0,1,2; 2D (x,z) -> 0,2
+    const int axis3[3] = {0, d == 3 ? 1 : 2, 2};
+    for (int p = 0; p < np; ++p) {
+        int64_t i0[3] = {0, 0, 0};
+        double f[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a) {
+            const int A = axis3[a];
+            const double c = P->coords[(size_t)p * d + a];
+            const double top = (double)(G.n[A] - 1) * G.h[A];
+            if (!(c >= 0.0) || !(c <= top))
+                return fail(WAVE_ERANGE, "%s point %d: coordinate %d = %.17g outside [0, %.17g]",
+                            what, p, a, c, top);
+            const double x = std::min(c / G.h[A], (double)(G.n[A] - 1));
+            int64_t i = (int64_t)std::floor(x);
+            if (i > G.n[A] - 2) i = G.n[A] - 2;
+            i0[A] = i;
+            f[A] = x - (double)i;
+        }
+        out->base[p] = (i0[0] * G.n[1] + i0[1]) * G.n[2] + i0[2];
+        for (int A = 0; A < 3; ++A) out->cell[(size_t)p * 3 + A] = i0[A];
+        for (int c = 0; c < nc; ++c) {
+            double w = 1.0;
+            for (int a = 0; a < d; ++a) {
+                const int bit = (c >> (d - 1 - a)) & 1;
+                const double fa = f[axis3[a]];
+                w *= bit ? fa : 1.0 - fa;
+            }
+            out->w[(size_t)p * nc + c] = (float)w;
+        }
+    }
+    return WAVE_OK;
+}
+
+// Owner-gather table for injection: every (point, corner) pair becomes one
+// entry keyed by the grid row and z of its node; entries are sorted by (row,
+// z, point) so each node sums its contributions in a fixed order.
+struct HostInject {
+    std::vector<int32_t> row_ptr;   // [nrows + 1]
+    std::vector<InjEntry> ent;
+};
+
+void make_inject(const Geo& G, const HostPoints& P, HostInject* out)
+{
+    const int d = G.ndim, nc = 1 << d;
+    out->ent.clear();
+    out->ent.reserve((size_t)P.npts * nc);
+    for (int p = 0; p < P.npts; ++p) {
+        const int64_t* i0 = &P.cell[(size_t)p * 3];
+        for (int c = 0; c < nc; ++c) {
+            int64_t idx[3] = {i0[0], i0[1], i0[2]};
+            if (d == 3) {
+                idx[0] += (c >> 2) & 1; idx[1] += (c >> 1) & 1; idx[2] += c & 1;
+            } else {
+                idx[0] += (c >> 1) & 1; idx[2] += c & 1;
+            }
+            InjEntry e;
+            e.row = (int32_t)(idx[0] * G.n[1] + idx[1]);
+            e.z = (int32_t)idx[2];
+            e.pt = p;
+            e.w = P.w[(size_t)p * nc + c];
+            out->ent.push_back(e);
+        }
+    }
+    std::stable_sort(out->ent.begin(), out->ent.end(), [](const InjEntry& a, const InjEntry& b) {
+        if (a.row != b.row) return a.row < b.row;
+        if (a.z != b.z) return a.z < b.z;
+        return a.pt < b.pt;
+    });
+    const int64_t nrows = G.nrows();
+    out->row_ptr.assign(nrows + 1, 0);
+    for (const InjEntry& e : out->ent) out->row_ptr[e.row + 1]++;
+    for (int64_t r = 0; r < nrows; ++r) out->row_ptr[r + 1] += out->row_ptr[r];
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout (one function for sizing and for carving).
+// ---------------------------------------------------------------------------
+struct Plan {
+    size_t alpha = 0, beta = 0, check = 0;
+    size_t wf[2] = {0, 0};                  // forward wavefield pair
+    size_t smp_base[2] = {0, 0}, smp_w[2] = {0, 0};   // [0]: receivers, [1]: sources
+    size_t inj_ptr[2] = {0, 0}, inj_ent[2] = {0, 0};  // [0]: sources, [1]: receivers
+    size_t ring = 0; int nring = 0;         // backward: forward replay buffers
+    size_t adj[2] = {0, 0};                 // adjoint wavefield pair
+    size_t resid = 0, dsyn = 0, red = 0;    // gradient: residual, modelled data, reduction
+    size_t ckpt = 0;                        // gradient: checkpoint storage
+    size_t total = 0;
+};
+
+struct Carver {
+    size_t off = 0;
+    size_t take(size_t bytes) { size_t o = off; off = round_up(off + std::max<size_t>(bytes, 1), kAlign); return o; }
+};
+
+int ckpt_every(const wave_opts* o) { return (o && o->ckpt_every > 0) ? o->ckpt_every : 20; }
+
+int ckpt_elem(const wave_opts* o)
+{
+    if (!o || o->ckpt_dtype == WAVE_CKPT_FP32) return 4;
+    return 2;
+}
+
+size_t ckpt_bytes(const Geo& G, const wave_opts* o)
+{
+    const int K = ckpt_every(o);
+    const int64_t nck = (G.nt + K - 1) / K;
+    const size_t snap = round_up((size_t)G.npts() * ckpt_elem(o), kAlign);
+    return (size_t)nck * 2 * snap + round_up((size_t)nck * 2 * sizeof(float), kAlign);
+}
+
+Plan make_plan(int op, const Geo& G, int nsrc, int nrec, const wave_opts* o)
+{
+    Plan P;
+    Carver c;
+    const size_t N = (size_t)G.npts();
+    const int nc = 1 << G.ndim;
+    P.alpha = c.take(N * 4);
+    P.beta = c.take(N * 4);
+    P.check = c.take((size_t)kCheckBlocks * 3 * 4);
+    const int npt[2] = {nrec, nsrc};
+    for (int s = 0; s < 2; ++s) {
+        P.smp_base[s] = c.take((size_t)npt[s] * 8);
+        P.smp_w[s] = c.take((size_t)npt[s] * nc * 4);
+    }
+    const int ipt[2] = {nsrc, nrec};
+    for (int s = 0; s < 2; ++s) {
+        P.inj_ptr[s] = c.take(((size_t)G.nrows() + 1) * 4);
+        P.inj_ent[s] = c.take((size_t)ipt[s] * nc * sizeof(InjEntry));
+    }
+    if (op == WAVE_OP_FORWARD || op == WAVE_OP_GRADIENT) {
+        P.wf[0] = c.take(N * 4);
+        P.wf[1] = c.take(N * 4);
+    }
+    if (op == WAVE_OP_ADJOINT || op == WAVE_OP_GRADIENT) {
+        P.adj[0] = c.take(N * 4);
+        P.adj[1] = c.take(N * 4);
+    }
+    if (op == WAVE_OP_GRADIENT) {
+        P.nring = std::min(ckpt_every(o), G.nt) + 1;
+        P.ring = c.take(N * 4 * (size_t)P.nring);
+        P.resid = c.take((size_t)G.nt * nrec * 4);
+        P.dsyn = c.take((size_t)G.nt * nrec * 4);
+        P.red = c.take(1024 * 4);
+        P.ckpt = c.take(ckpt_bytes(G, o));
+    }
+    P.total = c.off;
+    return P;
+}
+
+// ---------------------------------------------------------------------------
+// Per-call device context
+// ---------------------------------------------------------------------------
+struct Ctx {
+    Geo G;
+    Plan P;
+    char* ws = nullptr;
+    hipStream_t s = nullptr;
+    float cx[kMaxHalf + 1] = {}, cy[kMaxHalf + 1] = {}, cz[kMaxHalf + 1] = {};
+    HostPoints rec, src;
+    HostInject inj_src, inj_rec;
+    template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+int check_ws(const Plan& P, const wave_opts* o)
+{
+    if (!o) return fail(WAVE_EWORKSPACE, "opts is NULL (it carries the workspace)");
+    if (o->ckpt_dtype < WAVE_CKPT_FP32 || o->ckpt_dtype > WAVE_CKPT_FP16)
+        return fail(WAVE_EINVAL, "unknown ckpt_dtype %d", o->ckpt_dtype);
+    if (o->ckpt_every < 0) return fail(WAVE_EINVAL, "ckpt_every must be >= 0");
+    if (!o->workspace) return fail(WAVE_EWORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(o->workspace) % kAlign)
+        return fail(WAVE_EWORKSPACE, "workspace must be %zu-byte aligned", kAlign);
+    if (o->workspace_bytes < P.total)
+        return fail(WAVE_EWORKSPACE, "workspace too small: %zu bytes given, %zu needed",
+                    o->workspace_bytes, P.total);
+    return WAVE_OK;
+}
+
+void set_weights(Ctx& C)
+{
+    double c[kMaxHalf + 1];
+    fd_weights(C.G.half, c);
+    for (int j = 1; j <= C.G.half; ++j) {
+        C.cx[j] = (float)(c[j] / (C.G.h[0] * C.G.h[0]));
+        C.cy[j] = C.G.ndim == 3 ? (float)(c[j] / (C.G.h[1] * C.G.h[1])) : 0.f;
+        C.cz[j] = (float)(c[j] / (C.G.h[2] * C.G.h[2]));
+    }
+}
+
+// Common set-up: tables, uploads, field validation (one wait), coefficients.
+int setup(Ctx& C, int op, const wave_grid* grid, const float* m, const float* eta,
+          const wave_points* src, const wave_points* rec, const wave_opts* o, void* stream)
+{
+    int rc = make_geo(grid, &C.G);
+    if (rc) return rc;
+    if (!m) return fail(WAVE_EINVAL, "m is NULL");
+    if ((rc = make_points(C.G, rec, "receiver", &C.rec))) return rc;
+    if ((rc = make_points(C.G, src, "source", &C.src))) return rc;
+    C.P = make_plan(op, C.G, C.src.npts, C.rec.npts, o);
+    if ((rc = check_ws(C.P, o))) return rc;
+    C.ws = static_cast<char*>(o->workspace);
+    C.s = static_cast<hipStream_t>(stream);
+    set_weights(C);
+    make_inject(C.G, C.src, &C.inj_src);
+    make_inject(C.G, C.rec, &C.inj_rec);
+    const int nc = 1 << C.G.ndim;
+    const HostPoints* sp[2] = {&C.rec, &C.src};
+    for (int s = 0; s < 2; ++s) {
+        if (sp[s]->npts == 0) continue;
+        HIP_TRY(hipMemcpyAsync(C.at<void>(C.P.smp_base[s]), sp[s]->base.data(), sp[s]->npts * 8,
+                               hipMemcpyHostToDevice, C.s));
+        HIP_TRY(hipMemcpyAsync(C.at<void>(C.P.smp_w[s]), sp[s]->w.data(),
+                               (size_t)sp[s]->npts * nc * 4, hipMemcpyHostToDevice, C.s));
+    }
+    const HostInject* ij[2] = {&C.inj_src, &C.inj_rec};
+    for (int s = 0; s < 2; ++s) {
+        HIP_TRY(hipMemcpyAsync(C.at<void>(C.P.inj_ptr[s]), ij[s]->row_ptr.data(),
+                               ij[s]->row_ptr.size() * 4, hipMemcpyHostToDevice, C.s));
+        if (!ij[s]->ent.empty())
+            HIP_TRY(hipMemcpyAsync(C.at<void>(C.P.inj_ent[s]), ij[s]->ent.data(),
+                                   ij[s]->ent.size() * sizeof(InjEntry), hipMemcpyHostToDevice, C.s));
+    }
+    // field validation + stability bound: the only wait of the call
+    const int64_t N = C.G.npts();
+    HIP_TRY(launch_check_fields(m, eta, N, C.at<float>(C.P.check), kCheckBlocks, C.s));
+    std::vector<float> part((size_t)kCheckBlocks * 3);
+    HIP_TRY(hipMemcpyAsync(part.data(), C.at<float>(C.P.check), part.size() * 4,
+                           hipMemcpyDeviceToHost, C.s));
+    HIP_TRY(hipStreamSynchronize(C.s));
+    float mmin = INFINITY, bad = 0;
+    for (int b = 0; b < kCheckBlocks; ++b) {
+        mmin = std::min(mmin, part[3 * b]);
+        bad += part[3 * b + 2];
+    }
+    if (bad > 0)
+        return fail(WAVE_EINVAL, "%.0f entries of m/eta are invalid (need m finite > 0, eta finite >= 0)", bad);
+    const double vmax = 1.0 / std::sqrt((double)mmin);
+    const double dtmax = cfl_dt_max(C.G, vmax);
+    if (C.G.dt > dtmax)
+        return fail(WAVE_ECFL, "dt = %.9g exceeds the stability bound %.9g (vmax = %.6g, order %d)",
+                    C.G.dt, dtmax, vmax, C.G.order);
+    HIP_TRY(launch_coefficients(m, eta, C.at<float>(C.P.alpha), C.at<float>(C.P.beta), N,
+                                (float)C.G.dt, C.s));
+    return WAVE_OK;
+}
+
+StepArgs base_args(const Ctx& C)
+{
+    StepArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.alpha = C.at<float>(C.P.alpha);
+    a.beta = C.at<float>(C.P.beta);
+    a.nx = C.G.n[0]; a.ny = C.G.n[1]; a.nz = C.G.n[2];
+    std::memcpy(a.cx, C.cx, sizeof a.cx);
+    std::memcpy(a.cy, C.cy, sizeof a.cy);
+    std::memcpy(a.cz, C.cz, sizeof a.cz);
+    a.inv_dt2 = (float)(1.0 / (C.G.dt * C.G.dt));
+    return a;
+}
+
+// set = 0: sources inject (forward), receivers sample; set = 1: receivers
+// inject (adjoint), sources sample.
+void bind_sparse(const Ctx& C, StepArgs& a, int set)
+{
+    const int inj = set == 0 ? 0 : 1;
+    const int smp = set == 0 ? 0 : 1;
+    a.inj.row_ptr = C.at<int32_t>(C.P.inj_ptr[inj]);
+    a.inj.ent = C.at<InjEntry>(C.P.inj_ent[inj]);
+    a.smp.base = C.at<int64_t>(C.P.smp_base[smp]);
+    a.smp.w = C.at<float>(C.P.smp_w[smp]);
+    a.smp.npts = set == 0 ? C.rec.npts : C.src.npts;
+}
+
+hipError_t step(const Ctx& C, const StepArgs& a)
+{
+    ++g_prof.launches;
+    return launch_step(C.G.ndim, C.G.order, a, C.s);
+}
+
+struct CkptView {
+    char* base = nullptr;
+    int K = 20, elem = 4, nck = 0;
+    size_t snap = 0;
+    void* snapshot(int c, int which) const { return base + ((size_t)c * 2 + which) * snap; }
+    float* scale(int c, int which) const
+    {
+        return reinterpret_cast<float*>(base + (size_t)nck * 2 * snap) + (size_t)c * 2 + which;
+    }
+};
+
+CkptView ckpt_view(const Geo& G, const wave_opts* o, void* base)
+{
+    CkptView v;
+    v.base = static_cast<char*>(base);
+    v.K = ckpt_every(o);
+    v.elem = ckpt_elem(o);
+    v.nck = (G.nt + v.K - 1) / v.K;
+    v.snap = round_up((size_t)G.npts() * v.elem, kAlign);
+    return v;
+}
+
+int store_snapshot(const Ctx& C, const CkptView& v, int c, int which, const float* u)
+{
+    if (v.elem == 4) {
+        HIP_TRY(hipMemcpyAsync(v.snapshot(c, which), u, (size_t)C.G.npts() * 4,
+                               hipMemcpyDeviceToDevice, C.s));
+        return WAVE_OK;
+    }
+    return fail(WAVE_EINVAL, "reduced-precision checkpoints are not available yet");
+}
+
+int load_snapshot(const Ctx& C, const CkptView& v, int c, int which, float* u)
+{
+    if (v.elem == 4) {
+        HIP_TRY(hipMemcpyAsync(u, v.snapshot(c, which), (size_t)C.G.npts() * 4,
+                               hipMemcpyDeviceToDevice, C.s));
+        return WAVE_OK;
+    }
+    return fail(WAVE_EINVAL, "reduced-precision checkpoints are not available yet");
+}
+
+// Forward time loop over the two-buffer in-place leapfrog.  If `ck` is set,
+// the pair (u^c, u^{c-1}) is stored before step c for c = 0, K, 2K, ...
+int run_forward(const Ctx& C, const float* q, float* d, float* u_final, const CkptView* ck,
+                bool close_prof)
+{
+    const int64_t N = C.G.npts();
+    float* buf[2] = {C.at<float>(C.P.wf[0]), C.at<float>(C.P.wf[1])};
+    HIP_TRY(launch_fill(buf[0], N, 0.f, C.s));
+    HIP_TRY(launch_fill(buf[1], N, 0.f, C.s));
+    StepArgs a = base_args(C);
+    bind_sparse(C, a, 0);
+    int cur = 0;   // buf[cur] = u^n, buf[1-cur] = u^{n-1}
+    if (prof_begin(C.s)) return fail(WAVE_EHIP, "profiling event failed");
+    for (int n = 0; n < C.G.nt; ++n) {
+        if (ck && n % ck->K == 0) {
+            int rc = store_snapshot(C, *ck, n / ck->K, 0, buf[cur]);
+            if (!rc) rc = store_snapshot(C, *ck, n / ck->K, 1, buf[1 - cur]);
+            if (rc) return rc;
+        }
+        a.cur = buf[cur];
+        a.other = buf[1 - cur];
+        a.out = buf[1 - cur];
+        a.inj_val = C.src.npts ? q + (size_t)n * C.src.npts : nullptr;
+        a.smp_out = C.rec.npts ? d + (size_t)n * C.rec.npts : nullptr;
+        HIP_TRY(step(C, a));
+        cur = 1 - cur;
+    }
+    if (close_prof && prof_end(C.s)) return fail(WAVE_EHIP, "profiling event failed");
+    if (u_final)
+        HIP_TRY(hipMemcpyAsync(u_final, buf[cur], (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
+    return WAVE_OK;
+}
+
+// Backward pass: replay each checkpoint segment forward into the ring, then
+// step the adjoint through it with the imaging condition fused.
+int run_backward(const Ctx& C, const float* q, const float* r, const CkptView& ck, float* grad,
+                 float* grad_q, bool open_prof)
+{
+    const int64_t N = C.G.npts();
+    const int nt = C.G.nt;
+    float* v[2] = {C.at<float>(C.P.adj[0]), C.at<float>(C.P.adj[1])};
+    HIP_TRY(launch_fill(v[0], N, 0.f, C.s));
+    HIP_TRY(launch_fill(v[1], N, 0.f, C.s));
+    HIP_TRY(launch_fill(grad, N, 0.f, C.s));
+    float* ring = C.at<float>(C.P.ring);
+    auto slot = [&](int i) { return ring + (size_t)i * N; };
+    StepArgs fa = base_args(C);
+    bind_sparse(C, fa, 0);
+    fa.smp_out = nullptr;
+    StepArgs ba = base_args(C);
+    bind_sparse(C, ba, 1);
+    ba.img_grad = grad;
+    int vc = 0;    // v[vc] = v^k, v[1-vc] = v^{k+1}
+    if (open_prof && prof_begin(C.s)) return fail(WAVE_EHIP, "profiling event failed");
+    for (int seg = ck.nck - 1; seg >= 0; --seg) {
+        const int c0 = seg * ck.K;
+        const int c1 = std::min(c0 + ck.K, nt);
+        // ring slot i holds u^{c0 - 1 + i}
+        int rc = load_snapshot(C, ck, seg, 1, slot(0));
+        if (!rc) rc = load_snapshot(C, ck, seg, 0, slot(1));
+        if (rc) return rc;
+        for (int n = c0; n < c1 - 1; ++n) {
+            fa.cur = slot(n - c0 + 1);
+            fa.other = slot(n - c0);
+            fa.out = slot(n - c0 + 2);
+            fa.inj_val = C.src.npts ? q + (size_t)n * C.src.npts : nullptr;
+            HIP_TRY(step(C, fa));
+        }
+        for (int k = c1 - 1; k >= c0; --k) {
+            ba.cur = v[vc];
+            ba.other = v[1 - vc];
+            ba.out = v[1 - vc];
+            ba.inj_val = C.rec.npts ? r + (size_t)k * C.rec.npts : nullptr;
+            ba.smp_out = (grad_q && C.src.npts) ? grad_q + (size_t)k * C.src.npts : nullptr;
+            ba.img_fwd = slot(k - c0 + 1);
+            HIP_TRY(step(C, ba));
+            vc = 1 - vc;
+        }
+    }
+    if (prof_end(C.s)) return fail(WAVE_EHIP, "profiling event failed");
+    return WAVE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wave_last_error(void) { return g_error.c_str(); }
+
+const char* wave_version(void) { return "wavefd-mi355x 0.1 (gfx950)"; }
+
+int wave_set_profiling(int32_t enable)
+{
+    g_prof.on = enable != 0;
+    g_prof.have = false;
+    return WAVE_OK;
+}
+
+int wave_last_loop(double* ms, int64_t* launches)
+{
+    if (!ms || !launches) return fail(WAVE_EINVAL, "ms and launches are required");
+    if (!g_prof.have) return fail(WAVE_EINVAL, "no profiled call on this thread");
+    HIP_TRY(hipEventSynchronize(g_prof.t1));
+    float f = 0.f;
+    HIP_TRY(hipEventElapsedTime(&f, g_prof.t0, g_prof.t1));
+    *ms = f;
+    *launches = g_prof.launches;
+    return WAVE_OK;
+}
+
+int wave_workspace_size(int32_t op, const wave_grid* grid, const wave_points* src,
+                        const wave_points* rec, const wave_opts* opts, size_t* bytes)
+{
+    try {
+        if (!bytes) return fail(WAVE_EINVAL, "bytes is NULL");
+        if (op < WAVE_OP_FORWARD || op > WAVE_OP_GRADIENT) return fail(WAVE_EINVAL, "unknown op %d", op);
+        Geo G;
+        int rc = make_geo(grid, &G);
+        if (rc) return rc;
+        const int ns = src ? src->npts : 0, nr = rec ? rec->npts : 0;
+        if (ns < 0 || nr < 0) return fail(WAVE_EINVAL, "npts < 0");
+        *bytes = make_plan(op, G, ns, nr, opts).total;
+        return WAVE_OK;
+    } catch (const std::exception& e) {
+        return fail(WAVE_EINVAL, "exception: %s", e.what());
+    } catch (...) {
+        return fail(WAVE_EINVAL, "unknown exception");
+    }
+}
+
+int wave_checkpoint_size(const wave_grid* grid, const wave_opts* opts, size_t* bytes)
+{
+    if (!bytes) return fail(WAVE_EINVAL, "bytes is NULL");
+    Geo G;
+    int rc = make_geo(grid, &G);
+    if (rc) return rc;
+    if (opts && (opts->ckpt_dtype < WAVE_CKPT_FP32 || opts->ckpt_dtype > WAVE_CKPT_FP16))
+        return fail(WAVE_EINVAL, "unknown ckpt_dtype %d", opts->ckpt_dtype);
+    *bytes = ckpt_bytes(G, opts);
+    return WAVE_OK;
+}
+
+int wave_forward(const wave_grid* grid, const float* m, const float* eta, const wave_points* src,
+                 const float* q, const wave_points* rec, float* d, float* u_final, void* ckpt,
+                 const wave_opts* opts, void* stream)
+{
+    try {
+        Ctx C;
+        const int op = ckpt ? WAVE_OP_GRADIENT : WAVE_OP_FORWARD;
+        if (src && src->npts > 0 && !q) return fail(WAVE_EINVAL, "q is NULL with %d sources", src->npts);
+        if (rec && rec->npts > 0 && !d) return fail(WAVE_EINVAL, "d is NULL with %d receivers", rec->npts);
+        int rc = setup(C, op, grid, m, eta, src, rec, opts, stream);
+        if (rc) return rc;
+        CkptView ck;
+        if (ckpt) ck = ckpt_view(C.G, opts, ckpt);
+        return run_forward(C, q, d, u_final, ckpt ? &ck : nullptr, true);
+    } catch (const std::exception& e) {
+        return fail(WAVE_EINVAL, "exception: %s", e.what());
+    } catch (...) {
+        return fail(WAVE_EINVAL, "unknown exception");
+    }
+}
+
+int wave_adjoint(const wave_grid* grid, const float* m, const float* eta, const wave_points* rec,
+                 const float* d, const wave_points* src, float* q_adj, float* v_final,
+                 const wave_opts* opts, void* stream)
+{
+    try {
+        Ctx C;
+        if (src && src->npts > 0 && !q_adj) return fail(WAVE_EINVAL, "q_adj is NULL with %d sources", src->npts);
+        if (rec && rec->npts > 0 && !d) return fail(WAVE_EINVAL, "d is NULL with %d receivers", rec->npts);
+        int rc = setup(C, WAVE_OP_ADJOINT, grid, m, eta, src, rec, opts, stream);
+        if (rc) return rc;
+        const int64_t N = C.G.npts();
+        float* v[2] = {C.at<float>(C.P.adj[0]), C.at<float>(C.P.adj[1])};
+        HIP_TRY(launch_fill(v[0], N, 0.f, C.s));
+        HIP_TRY(launch_fill(v[1], N, 0.f, C.s));
+        StepArgs a = base_args(C);
+        bind_sparse(C, a, 1);
+        int vc = 0;
+        if (prof_begin(C.s)) return fail(WAVE_EHIP, "profiling event failed");
+        for (int k = C.G.nt - 1; k >= 0; --k) {
+            a.cur = v[vc];
+            a.other = v[1 - vc];
+            a.out = v[1 - vc];
+            a.inj_val = C.rec.npts ? d + (size_t)k * C.rec.npts : nullptr;
+            a.smp_out = C.src.npts ? q_adj + (size_t)k * C.src.npts : nullptr;
+            HIP_TRY(step(C, a));
+            vc = 1 - vc;
+        }
+        if (prof_end(C.s)) return fail(WAVE_EHIP, "profiling event failed");
+        // v[1 - vc] holds v^0 (the state sampled last)
+        if (v_final)
+            HIP_TRY(hipMemcpyAsync(v_final, v[1 - vc], (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
+        return WAVE_OK;
+    } catch (const std::exception& e) {
+        return fail(WAVE_EINVAL, "exception: %s", e.what());
+    } catch (...) {
+        return fail(WAVE_EINVAL, "unknown exception");
+    }
+}
+
+int wave_backward(const wave_grid* grid, const float* m, const float* eta, const wave_points* src,
+                  const float* q, const wave_points* rec, const float* r, const void* ckpt,
+                  float* grad_m, float* grad_q, const wave_opts* opts, void* stream)
+{
+    try {
+        Ctx C;
+        if (!ckpt) return fail(WAVE_EINVAL, "ckpt is NULL");
+        if (!grad_m) return fail(WAVE_EINVAL, "grad_m is NULL");
+        if (src && src->npts > 0 && !q) return fail(WAVE_EINVAL, "q is NULL with %d sources", src->npts);
+        if (rec && rec->npts > 0 && !r) return fail(WAVE_EINVAL, "r is NULL with %d receivers", rec->npts);
+        int rc = setup(C, WAVE_OP_GRADIENT, grid, m, eta, src, rec, opts, stream);
+        if (rc) return rc;
+        CkptView ck = ckpt_view(C.G, opts, const_cast<void*>(ckpt));
+        return run_backward(C, q, r, ck, grad_m, grad_q, true);
+    } catch (const std::exception& e) {
+        return fail(WAVE_EINVAL, "exception: %s", e.what());
+    } catch (...) {
+        return fail(WAVE_EINVAL, "unknown exception");
+    }
+}
+
+int wave_gradient(const wave_grid* grid, const float* m, const float* eta, const wave_points* src,
+                  const float* q, const wave_points* rec, const float* d_obs, float* grad,
+                  float* misfit, float* d_syn, const wave_opts* opts, void* stream)
+{
+    try {
+        Ctx C;
+        if (!grad || !misfit || !d_obs) return fail(WAVE_EINVAL, "grad, misfit and d_obs are required");
+        if (!rec || rec->npts <= 0) return fail(WAVE_EINVAL, "the gradient needs receivers");
+        if (src && src->npts > 0 && !q) return fail(WAVE_EINVAL, "q is NULL with %d sources", src->npts);
+        int rc = setup(C, WAVE_OP_GRADIENT, grid, m, eta, src, rec, opts, stream);
+        if (rc) return rc;
+        CkptView ck = ckpt_view(C.G, opts, C.at<void>(C.P.ckpt));
+        float* dsyn = d_syn ? d_syn : C.at<float>(C.P.dsyn);
+        rc = run_forward(C, q, dsyn, nullptr, &ck, false);
+        if (rc) return rc;
+        const int64_t nd = (int64_t)C.G.nt * C.rec.npts;
+        float* resid = C.at<float>(C.P.resid);
+        HIP_TRY(launch_residual(dsyn, d_obs, resid, nd, C.at<float>(C.P.red), 1024, misfit, C.s));
+        return run_backward(C, q, resid, ck, grad, nullptr, false);
+    } catch (const std::exception& e) {
+        return fail(WAVE_EINVAL, "exception: %s", e.what());
+    } catch (...) {
+        return fail(WAVE_EINVAL, "unknown exception");
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// Internal interface between the host orchestration (wave_host.cpp) and the
+// gfx950 kernels (wave_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wave {
+
+constexpr int kMaxHalf = 8;        // space order 16 -> half-width 8
+
+// One injection contribution, sorted by (row, z, point): the owner of grid
+// node (row, z) adds alpha * w * val[pt] to its update.  row = x*ny + y (3D)
+// or x (2D).
+struct InjEntry {
+    int32_t z;
+    int32_t pt;
+    float w;
+    int32_t row;
+};
+
+// Device view of a set of sparse points used for sampling: flat index of the
+// cell's lowest corner and the 2^d multilinear weights (corner bit a selects
+// +1 along axis a, axis 0 most significant).
+struct SampleSet {
+    const int64_t* base;   // [npts]
+    const float* w;        // [npts][2^d]
+    int32_t npts;
+};
+
+struct InjectSet {
+    const int32_t* row_ptr;   // [nrows + 1]
+    const InjEntry* ent;      // [nent]
+};
+
+// Everything one time step needs.  `out` may alias `other` (in-place
+// leapfrog: u^{n+1} overwrites u^{n-1}, each point is read then written by
+// the same thread only).
+struct StepArgs {
+    const float* cur;      // u^n (forward) / v^k (adjoint)
+    const float* other;    // u^{n-1} / v^{k+1}
+    float* out;            // u^{n+1} / v^{k-1}
+    const float* alpha;    // dt^2 / (m + eta dt/2)
+    const float* beta;     // (m - eta dt/2) / (m + eta dt/2)
+    int64_t nx, ny, nz;    // 2D: ny = 1
+    float cx[kMaxHalf + 1], cy[kMaxHalf + 1], cz[kMaxHalf + 1];   // c_j / h^2, j >= 1
+    // injection into `out` (values for this step)
+    InjectSet inj;
+    const float* inj_val;  // [npts of the injected set] for this step, or nullptr
+    // sampling of `cur` (values for this step)
+    SampleSet smp;
+    float* smp_out;        // [npts] for this step, or nullptr
+    int64_t stencil_blocks;
+    // imaging condition (adjoint with gradient): g -= fwd * (other - 2 cur + out) / dt^2
+    const float* img_fwd;  // u^k, or nullptr
+    float* img_grad;
+    float inv_dt2;
+};
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_step(int ndim, int order, const StepArgs& a, hipStream_t s);
+hipError_t launch_coefficients(const float* m, const float* eta, float* alpha, float* beta,
+                               int64_t n, float dt, hipStream_t s);
+// Partial reductions for validation: per block {min m, min eta (0 if eta null),
+// count of bad values}.  `partial` holds 3 * nblocks floats.
+hipError_t launch_check_fields(const float* m, const float* eta, int64_t n, float* partial,
+                               int nblocks, hipStream_t s);
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
+// r = d - dobs over n values and misfit[0] = 1/2 sum r^2 (deterministic two-pass
+// reduction through `partial`, which holds nblocks floats).
+hipError_t launch_residual(const float* d, const float* dobs, float* r, int64_t n, float* partial,
+                           int nblocks, float* misfit, hipStream_t s);
+
+}  // namespace wave

@@ -1,0 +1,116 @@
+"""Adjoint and gradient parity: the HIP adjoint against the oracle adjoint,
+the FP32 dot test, the gradient (checkpointed replay) against the oracle
+gradient, and checkpoint-interval invariance."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import device_inputs, rel_l2
+from paper_1609_03361_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+@pytest.mark.parametrize("shape,order", [((40, 52), 4), ((31, 29, 27), 8), ((36, 33), 16)])
+def test_adjoint_matches_oracle(dev, shape, order):
+    import torch
+    from paper_1609_03361_amd import api
+    p = synth.random_problem(shape, order, 40, seed=order, nsrc=3, nrec=13)
+    print(f"case {p.name}", flush=True)
+    geom, m, eta, q = device_inputs(p, dev)
+    rng = np.random.default_rng(2)
+    dres = rng.standard_normal((p.nt, p.rec.shape[0])).astype(np.float32)
+    qa, v0 = api.adjoint(geom, m, eta, torch.from_numpy(dres).to(dev), return_final=True)
+    torch.cuda.synchronize()
+    ref = oracle.adjoint(p.shape, p.spacing, p.order, p.dt, p.nt, p.m, p.eta, p.rec, dres, p.src)
+    assert rel_l2(qa.cpu().numpy(), ref["qadj"]) < 1e-5
+    assert rel_l2(v0.cpu().numpy(), ref["v"]) < 1e-5
+
+
+@pytest.mark.parametrize("shape,order", [((60, 70), 8), ((30, 28, 33), 4), ((26, 30, 31), 16)])
+def test_dot_product_fp32(dev, shape, order):
+    import torch
+    from paper_1609_03361_amd import api
+    p = synth.random_problem(shape, order, 60, seed=3 * order, nsrc=4, nrec=15)
+    geom, m, eta, q = device_inputs(p, dev)
+    rng = np.random.default_rng(5)
+    y = torch.from_numpy(rng.standard_normal((p.nt, p.rec.shape[0])).astype(np.float32)).to(dev)
+    Fx = api.forward(geom, m, eta, q)
+    FTy = api.adjoint(geom, m, eta, y)
+    torch.cuda.synchronize()
+    lhs = float((Fx.double() * y.double()).sum())
+    rhs = float((q.double() * FTy.double()).sum())
+    print(f"dot {p.name}: {lhs!r} {rhs!r} rel {abs(1 - lhs / rhs):.2e}", flush=True)
+    assert abs(1.0 - lhs / rhs) < 1e-5
+
+
+def _gradient_case(shape, order, nt, seed=21):
+    from scipy.ndimage import gaussian_filter
+    p = synth.random_problem(shape, order, nt, seed=seed, nsrc=2, nrec=17)
+    rng = np.random.default_rng(5)
+    dm = gaussian_filter(rng.standard_normal(shape), 2.0)
+    dm *= 0.05 * float(np.mean(p.m)) / np.max(np.abs(dm))
+    m_true = (p.m.astype(np.float64) + dm).astype(np.float32)
+    d_obs = oracle.forward(p.shape, p.spacing, p.order, p.dt, p.nt, m_true, p.eta, p.src, p.q,
+                           p.rec, want_final=False)["d"].astype(np.float32)
+    return p, d_obs
+
+
+@pytest.mark.parametrize("shape,order,nt,every", [((44, 40), 8, 90, 20), ((24, 22, 26), 8, 70, 16),
+                                                  ((30, 33), 4, 41, 41)])
+def test_gradient_matches_oracle(dev, shape, order, nt, every):
+    import torch
+    from paper_1609_03361_amd import api
+    p, d_obs = _gradient_case(shape, order, nt)
+    print(f"case {p.name} every={every}", flush=True)
+    geom, m, eta, q = device_inputs(p, dev)
+    J, g = api.gradient(geom, m, eta, q, torch.from_numpy(d_obs).to(dev), ckpt_every=every)
+    torch.cuda.synchronize()
+    ref = oracle.gradient(p.shape, p.spacing, p.order, p.dt, p.nt, p.m, p.eta, p.src, p.q, p.rec,
+                          d_obs)
+    eg = rel_l2(g.cpu().numpy(), ref["grad"])
+    ej = abs(float(J) - ref["J"]) / ref["J"]
+    print(f"gradient rel L2 {eg:.2e}  misfit rel {ej:.2e}", flush=True)
+    assert eg < 1e-4
+    assert ej < 1e-5
+
+
+def test_fp32_checkpoint_interval_does_not_change_the_gradient(dev):
+    import torch
+    from paper_1609_03361_amd import api
+    p, d_obs = _gradient_case((36, 34), 8, 64)
+    geom, m, eta, q = device_inputs(p, dev)
+    do = torch.from_numpy(d_obs).to(dev)
+    out = [api.gradient(geom, m, eta, q, do, ckpt_every=k) for k in (64, 20, 7, 1)]
+    torch.cuda.synchronize()
+    for J, g in out[1:]:
+        assert torch.equal(g, out[0][1])
+        assert torch.equal(J, out[0][0])
+
+
+def test_autograd_matches_gradient(dev):
+    import torch
+    from paper_1609_03361_amd import api
+    p, d_obs = _gradient_case((34, 38), 8, 50)
+    geom, m, eta, q = device_inputs(p, dev)
+    do = torch.from_numpy(d_obs).to(dev)
+    mt = m.clone().requires_grad_(True)
+    qt = q.clone().requires_grad_(True)
+    d = api.wave_apply(geom, mt, qt, eta, ckpt_every=10)
+    J = 0.5 * ((d - do) ** 2).sum()
+    J.backward()
+    Jr, gr = api.gradient(geom, m, eta, q, do, ckpt_every=10)
+    torch.cuda.synchronize()
+    assert rel_l2(mt.grad.cpu().numpy(), gr.cpu().numpy()) < 1e-6
+    # dJ/dq = F^T (d - d_obs)
+    r = (d.detach() - do)
+    ga = api.adjoint(geom, m, eta, r.contiguous())
+    torch.cuda.synchronize()
+    assert rel_l2(qt.grad.cpu().numpy(), ga.cpu().numpy()) < 1e-6

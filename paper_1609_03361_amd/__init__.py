@@ -12,8 +12,8 @@ __version__ = "0.1.0"
 def __getattr__(name):
     # the torch-facing API is loaded on first use, so that importing the
     # package (e.g. for ``synth``) does not require torch or the library
-    if name in ("api", "Geometry", "forward", "adjoint", "backward", "gradient", "WaveFn",
+    if name in ("Geometry", "forward", "adjoint", "backward", "gradient", "WaveFn",
                 "wave_apply", "checkpoint_bytes"):
-        from . import api
-        return api if name == "api" else getattr(api, name)
+        import importlib
+        return getattr(importlib.import_module(__name__ + ".api"), name)
     raise AttributeError(name)

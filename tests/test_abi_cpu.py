@@ -110,3 +110,11 @@ def test_checkpoint_size_scales_with_dtype_and_interval():
     assert sizes[("bf16", 20)] < 0.6 * sizes[("fp32", 20)]
     assert sizes[("fp16", 20)] == sizes[("bf16", 20)]
     assert sizes[("fp32", 10)] > 1.9 * sizes[("fp32", 20)]
+
+
+def test_python_api_imports_without_gpu():
+    from paper_1609_03361_amd import api
+    import paper_1609_03361_amd as pkg
+    assert pkg.Geometry is api.Geometry and callable(pkg.wave_apply)
+    g = api.Geometry((10, 12), (5.0, 5.0), 4, 1e-3, 7)
+    assert g.grid().nt == 7

@@ -47,8 +47,13 @@ def test_dot_product_fp32(dev, shape, order):
     torch.cuda.synchronize()
     lhs = float((Fx.double() * y.double()).sum())
     rhs = float((q.double() * FTy.double()).sum())
-    print(f"dot {p.name}: {lhs!r} {rhs!r} rel {abs(1 - lhs / rhs):.2e}", flush=True)
-    assert abs(1.0 - lhs / rhs) < 1e-5
+    # FP32 F and F^T are each accurate to ~1e-6 relative in norm; a random y
+    # makes <Fx, y> a cancelling sum, so the mismatch is measured against the
+    # norms that bound it: |<Fx,y> - <x,F^T y>| <= tol (|Fx||y| + |x||F^T y|).
+    scale = float(Fx.double().norm() * y.double().norm() + q.double().norm() * FTy.double().norm())
+    print(f"dot {p.name}: {lhs!r} {rhs!r} ratio-1 {lhs / rhs - 1:.2e} "
+          f"normalised {abs(lhs - rhs) / scale:.2e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-6 * scale
 
 
 def _gradient_case(shape, order, nt, seed=21):
@@ -76,10 +81,15 @@ def test_gradient_matches_oracle(dev, shape, order, nt, every):
     ref = oracle.gradient(p.shape, p.spacing, p.order, p.dt, p.nt, p.m, p.eta, p.src, p.q, p.rec,
                           d_obs)
     eg = rel_l2(g.cpu().numpy(), ref["grad"])
-    ej = abs(float(J) - ref["J"]) / ref["J"]
-    print(f"gradient rel L2 {eg:.2e}  misfit rel {ej:.2e}", flush=True)
+    # J = 1/2 |d - d_obs|^2: an FP32 error dd in the traces moves J by about
+    # <r, dd>, so the misfit is held to 1e-5 |r| |d| rather than 1e-5 J
+    r_ref = ref["d"] - d_obs
+    bound = 1e-5 * np.linalg.norm(r_ref) * np.linalg.norm(ref["d"])
+    ej = abs(float(J) - ref["J"])
+    print(f"gradient rel L2 {eg:.2e}  misfit rel {ej / ref['J']:.2e} "
+          f"(bound {bound / ref['J']:.2e})", flush=True)
     assert eg < 1e-4
-    assert ej < 1e-5
+    assert ej <= bound
 
 
 def test_fp32_checkpoint_interval_does_not_change_the_gradient(dev):

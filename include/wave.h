@@ -85,7 +85,7 @@ typedef struct {
     size_t workspace_bytes;
     int32_t ckpt_every;       /* gradient/checkpointing: steps per segment, 0 = 20 */
     int32_t ckpt_dtype;       /* wave_ckpt_dtype for stored snapshots */
-    int32_t tile;             /* 0 = automatic, > 0 = explicit kernel tile id */
+    int32_t tile;             /* 0 = automatic, > 0 = x-chunk length (planes per block) */
     int32_t flags;            /* reserved, set to 0 */
 } wave_opts;
 

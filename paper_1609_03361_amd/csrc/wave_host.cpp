@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <string>
@@ -255,6 +256,7 @@ struct Plan {
     size_t smp_base[2] = {0, 0}, smp_w[2] = {0, 0};   // [0]: receivers, [1]: sources
     size_t inj_ptr[2] = {0, 0}, inj_ent[2] = {0, 0};  // [0]: sources, [1]: receivers
     size_t ring = 0; int nring = 0;         // backward: forward replay buffers
+    size_t gacc = 0;                        // backward: gradient accumulator
     size_t adj[2] = {0, 0};                 // adjoint wavefield pair
     size_t resid = 0, dsyn = 0, red = 0;    // gradient: residual, modelled data, reduction
     size_t ckpt = 0;                        // gradient: checkpoint storage
@@ -312,6 +314,7 @@ Plan make_plan(int op, const Geo& G, int nsrc, int nrec, const wave_opts* o)
     if (op == WAVE_OP_GRADIENT) {
         P.nring = std::min(ckpt_every(o), G.nt) + 1;
         P.ring = c.take(N * 4 * (size_t)P.nring);
+        P.gacc = c.take(N * 4);
         P.resid = c.take((size_t)G.nt * nrec * 4);
         P.dsyn = c.take((size_t)G.nt * nrec * 4);
         P.red = c.take(1024 * 4);
@@ -332,6 +335,8 @@ struct Ctx {
     float cx[kMaxHalf + 1] = {}, cy[kMaxHalf + 1] = {}, cz[kMaxHalf + 1] = {};
     HostPoints rec, src;
     HostInject inj_src, inj_rec;
+    int kernel = kStream;   // step kernel variant
+    int xchunk = 0;         // x-chunk length of the streaming kernel (0 = automatic)
     template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
 
@@ -374,6 +379,8 @@ int setup(Ctx& C, int op, const wave_grid* grid, const float* m, const float* et
     if ((rc = check_ws(C.P, o))) return rc;
     C.ws = static_cast<char*>(o->workspace);
     C.s = static_cast<hipStream_t>(stream);
+    C.xchunk = o->tile > 0 ? o->tile : 0;
+    if (const char* k = std::getenv("WAVE_STEP_KERNEL")) C.kernel = std::strcmp(k, "naive") ? kStream : kNaive;
     set_weights(C);
     make_inject(C.G, C.src, &C.inj_src);
     make_inject(C.G, C.rec, &C.inj_rec);
@@ -448,7 +455,7 @@ void bind_sparse(const Ctx& C, StepArgs& a, int set)
 hipError_t step(const Ctx& C, const StepArgs& a)
 {
     ++g_prof.launches;
-    return launch_step(C.G.ndim, C.G.order, a, C.s);
+    return launch_step(C.G.ndim, C.G.order, a, C.s, C.kernel, C.xchunk);
 }
 
 struct CkptView {
@@ -536,7 +543,8 @@ int run_backward(const Ctx& C, const float* q, const float* r, const CkptView& c
     float* v[2] = {C.at<float>(C.P.adj[0]), C.at<float>(C.P.adj[1])};
     HIP_TRY(launch_fill(v[0], N, 0.f, C.s));
     HIP_TRY(launch_fill(v[1], N, 0.f, C.s));
-    HIP_TRY(launch_fill(grad, N, 0.f, C.s));
+    float* gacc = C.at<float>(C.P.gacc);
+    HIP_TRY(launch_fill(gacc, N, 0.f, C.s));
     float* ring = C.at<float>(C.P.ring);
     auto slot = [&](int i) { return ring + (size_t)i * N; };
     StepArgs fa = base_args(C);
@@ -544,7 +552,7 @@ int run_backward(const Ctx& C, const float* q, const float* r, const CkptView& c
     fa.smp_out = nullptr;
     StepArgs ba = base_args(C);
     bind_sparse(C, ba, 1);
-    ba.img_grad = grad;
+    ba.img_grad = gacc;
     int vc = 0;    // v[vc] = v^k, v[1-vc] = v^{k+1}
     if (open_prof && prof_begin(C.s)) return fail(WAVE_EHIP, "profiling event failed");
     for (int seg = ck.nck - 1; seg >= 0; --seg) {
@@ -573,6 +581,7 @@ int run_backward(const Ctx& C, const float* q, const float* r, const CkptView& c
         }
     }
     if (prof_end(C.s)) return fail(WAVE_EHIP, "profiling event failed");
+    HIP_TRY(hipMemcpyAsync(grad, gacc, (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
     return WAVE_OK;
 }
 

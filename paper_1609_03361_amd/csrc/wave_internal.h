@@ -51,14 +51,24 @@ struct StepArgs {
     SampleSet smp;
     float* smp_out;        // [npts] for this step, or nullptr
     int64_t stencil_blocks;
+    // streaming-kernel tiling (set by the launcher): tiles along z and y,
+    // x-chunk length, and whether to remap block ids so that consecutive
+    // tiles land on the same XCD
+    int32_t ntz, nty, xchunk, remap;
     // imaging condition (adjoint with gradient): g -= fwd * (other - 2 cur + out) / dt^2
     const float* img_fwd;  // u^k, or nullptr
     float* img_grad;
     float inv_dt2;
 };
 
-// Launchers (return hipError_t of the launch).
-hipError_t launch_step(int ndim, int order, const StepArgs& a, hipStream_t s);
+// Kernel variants of the time step.  kStream: 2.5D register-streaming along
+// x with (y, z) planes staged in LDS; kNaive: one thread per point.
+enum StepKernel { kStream = 0, kNaive = 1 };
+
+// Launchers (return hipError_t of the launch).  `xchunk` <= 0 picks the
+// x-chunk length automatically.
+hipError_t launch_step(int ndim, int order, const StepArgs& a, hipStream_t s,
+                       int kernel = kStream, int xchunk = 0);
 hipError_t launch_coefficients(const float* m, const float* eta, float* alpha, float* beta,
                                int64_t n, float dt, hipStream_t s);
 // Partial reductions for validation: per block {min m, min eta (0 if eta null),

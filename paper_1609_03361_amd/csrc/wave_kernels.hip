@@ -13,6 +13,8 @@
 // sampling needs no ordering with the update.
 #include "wave_internal.h"
 
+#include <utility>
+
 namespace wave {
 
 namespace {
@@ -109,8 +111,263 @@ __global__ __launch_bounds__(kBlock) void k_step_naive(StepArgs a)
     a.out[i] = v;
 }
 
+// ---------------------------------------------------------------------------
+// 2.5D streaming step.  A block owns a (TY x TZ) tile of the (y, z) plane and
+// walks an x-chunk plane by plane.  Each thread keeps the 2R+1 x-neighbours of
+// its VZ consecutive z-points in a register queue (plus one slot being
+// filled), so the x part of the stencil costs no memory traffic; the current
+// plane with its y and z halos is staged in a double-buffered LDS tile for the
+// y and z parts.  The next plane's global loads are issued before the current
+// plane is computed.  Arithmetic per point, in order: x terms, y terms, z terms,
+// each lap = fma(c_j, (u[+j] + u[-j]) - 2 u[0], lap); then
+// out = fma(alpha, lap, fma(beta, u - other, u)).
+// ---------------------------------------------------------------------------
+template <int VZ>
+using Vec = float __attribute__((ext_vector_type(VZ)));
+
+template <int VZ>
+__device__ __forceinline__ Vec<VZ> vzero()
+{
+    return Vec<VZ>(0.f);
+}
+
+template <int VZ>
+__device__ __forceinline__ Vec<VZ> vload(const float* p)
+{
+    return *reinterpret_cast<const Vec<VZ>*>(p);
+}
+
+template <int VZ>
+__device__ __forceinline__ void vstore(float* p, const Vec<VZ>& v)
+{
+    *reinterpret_cast<Vec<VZ>*>(p) = v;
+}
+
+// Wait for this wave's LDS traffic, then meet the block at the barrier.
+// Outstanding global loads stay in flight across it (no vmcnt wait).
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <int DIM, int R, int VZ, int TZL, int TY>
+struct Tile {
+    static constexpr int NT = TZL * TY;
+    static constexpr int TZ = TZL * VZ;
+    static constexpr int RZ = (R + VZ - 1) / VZ * VZ;       // z halo, whole vectors
+    static constexpr int PITCH = TZ + 2 * RZ;
+    static constexpr int ROWS = DIM == 3 ? TY + 2 * R : TY;
+    static constexpr int NHY = DIM == 3 ? 2 * R * TZL : 0;   // y-halo vectors per plane
+    static constexpr int NHZ = TY * 2 * (RZ / VZ);          // z-halo vectors per plane
+    static constexpr int KH = (NHY + NHZ + NT - 1) / NT;    // halo vectors per thread
+    static constexpr int S = 2 * R + 2;                     // queue slots
+};
+
+template <int DIM, int R, int VZ, int TZL, int TY, bool IMG>
+__global__ __launch_bounds__(TZL* TY) void k_step_stream(StepArgs a)
+{
+    using T = Tile<DIM, R, VZ, TZL, TY>;
+    constexpr int NT = T::NT, TZ = T::TZ, RZ = T::RZ, PITCH = T::PITCH, S = T::S, KH = T::KH;
+    __shared__ __attribute__((aligned(16))) float lds[2][T::ROWS * PITCH];
+
+    const int64_t nx = a.nx, ny = a.ny, nz = a.nz;
+    const int64_t sy = nz, sx = ny * nz;
+    const int64_t b = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (b >= a.stencil_blocks) {
+        const int64_t p = (b - a.stencil_blocks) * NT + tid;
+        if (p < a.smp.npts) a.smp_out[p] = sample_point<DIM>(a.smp, a.cur, p, sy, sx);
+        return;
+    }
+    int64_t L = b;
+    if (a.remap) L = (b & 7) * (a.stencil_blocks >> 3) + (b >> 3);
+    const int tzi = (int)(L % a.ntz);
+    const int64_t t1 = L / a.ntz;
+    const int tyi = (int)(t1 % a.nty);
+    const int64_t chunk = t1 / a.nty;
+    const int tz = tid % TZL, ty = tid / TZL;
+    const int64_t y0 = (int64_t)tyi * TY, z0 = (int64_t)tzi * TZ;
+    const int64_t y = y0 + ty, z = z0 + (int64_t)tz * VZ;
+    const bool own = (y < ny) && (z < nz);
+    const int64_t col = y * sy + z;
+    const int64_t xa = chunk * a.xchunk;
+    const int64_t xb = xa + a.xchunk < nx ? xa + a.xchunk : nx;
+
+    // halo items of this thread: plane offset (or -1 when outside the grid) and LDS slot
+    int64_t hoff[KH];
+    int hlds[KH];
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+        const int i = tid + k * NT;
+        hoff[k] = -1;
+        hlds[k] = -1;
+        if (i < T::NHY) {
+            const int hr = i / TZL, hz = i % TZL;
+            const int64_t yy = hr < R ? y0 - R + hr : y0 + TY + (hr - R);
+            const int64_t zz = z0 + (int64_t)hz * VZ;
+            hlds[k] = (hr < R ? hr : hr + TY) * PITCH + RZ + hz * VZ;
+            if (yy >= 0 && yy < ny && zz < nz) hoff[k] = yy * sy + zz;
+        } else if (i < T::NHY + T::NHZ) {
+            constexpr int PER = RZ / VZ;
+            const int j = i - T::NHY;
+            const int r = j / (2 * PER), side = (j / PER) % 2, kk = j % PER;
+            const int64_t yy = y0 + r;
+            const int64_t zz = side == 0 ? z0 - RZ + (int64_t)kk * VZ : z0 + TZ + (int64_t)kk * VZ;
+            hlds[k] = (r + (DIM == 3 ? R : 0)) * PITCH + (side == 0 ? kk * VZ : RZ + TZ + kk * VZ);
+            if (yy < ny && zz >= 0 && zz < nz) hoff[k] = yy * sy + zz;
+        }
+    }
+
+    const float* __restrict__ u = a.cur;
+    auto center = [&](int64_t xx) -> Vec<VZ> {
+        Vec<VZ> r = vzero<VZ>();
+        if (own && xx >= 0 && xx < nx) r = vload<VZ>(u + xx * sx + col);
+        return r;
+    };
+
+    Vec<VZ> Q[S];
+#pragma unroll
+    for (int k = 0; k < 2 * R + 1; ++k) Q[k] = center(xa - R + k);
+    Q[S - 1] = vzero<VZ>();
+
+    // per-plane operands, double-buffered so plane x+1 is in flight while x is computed
+    struct Pre {
+        Vec<VZ> halo[KH];
+        Vec<VZ> uo, al, be;
+    };
+    Pre pre0, pre1;
+    auto fetch = [&](Pre& P, int64_t xx) {
+#pragma unroll
+        for (int k = 0; k < KH; ++k) {
+            P.halo[k] = vzero<VZ>();
+            if (hoff[k] >= 0) P.halo[k] = vload<VZ>(u + xx * sx + hoff[k]);
+        }
+        P.uo = P.al = P.be = vzero<VZ>();
+        if (own) {
+            P.uo = vload<VZ>(a.other + xx * sx + col);
+            P.al = vload<VZ>(a.alpha + xx * sx + col);
+            P.be = vload<VZ>(a.beta + xx * sx + col);
+        }
+    };
+    if (xa < xb) fetch(pre0, xa);
+
+    const int row_c = (ty + (DIM == 3 ? R : 0)) * PITCH + RZ + tz * VZ;
+
+    // one plane; U is the position within the unrolled group of S planes
+    auto plane = [&](auto UC, int64_t x) {
+        constexpr int U = decltype(UC)::value;
+        constexpr int B = U & 1;
+        Pre& P = B ? pre1 : pre0;
+        if (x + 1 < xb) fetch(B ? pre0 : pre1, x + 1);
+        Q[(U + 2 * R + 1) % S] = center(x + R + 1);
+        float* Ls = lds[B];
+        const Vec<VZ> c = Q[(U + R) % S];
+        vstore<VZ>(Ls + row_c, c);
+#pragma unroll
+        for (int k = 0; k < KH; ++k)
+            if (hlds[k] >= 0) vstore<VZ>(Ls + hlds[k], P.halo[k]);
+        lds_barrier();
+
+        float lap[VZ], m2c[VZ];
+#pragma unroll
+        for (int v = 0; v < VZ; ++v) {
+            lap[v] = 0.f;
+            m2c[v] = -2.f * c[v];
+        }
+#pragma unroll
+        for (int j = 1; j <= R; ++j) {
+            const Vec<VZ>& p = Q[(U + R + j) % S];
+            const Vec<VZ>& m = Q[(U + R - j + S) % S];
+#pragma unroll
+            for (int v = 0; v < VZ; ++v) lap[v] = fmaf(a.cx[j], (p[v] + m[v]) + m2c[v], lap[v]);
+        }
+        if (DIM == 3) {
+#pragma unroll
+            for (int j = 1; j <= R; ++j) {
+                const Vec<VZ> p = vload<VZ>(Ls + row_c + j * PITCH);
+                const Vec<VZ> m = vload<VZ>(Ls + row_c - j * PITCH);
+#pragma unroll
+                for (int v = 0; v < VZ; ++v)
+                    lap[v] = fmaf(a.cy[j], (p[v] + m[v]) + m2c[v], lap[v]);
+            }
+        }
+        {
+            float zr[2 * RZ + VZ];
+#pragma unroll
+            for (int k = 0; k < RZ / VZ; ++k) {
+                const Vec<VZ> lv = vload<VZ>(Ls + row_c - RZ + k * VZ);
+                const Vec<VZ> rv = vload<VZ>(Ls + row_c + VZ + k * VZ);
+#pragma unroll
+                for (int v = 0; v < VZ; ++v) {
+                    zr[k * VZ + v] = lv[v];
+                    zr[RZ + VZ + k * VZ + v] = rv[v];
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < VZ; ++v) zr[RZ + v] = c[v];
+#pragma unroll
+            for (int j = 1; j <= R; ++j)
+#pragma unroll
+                for (int v = 0; v < VZ; ++v)
+                    lap[v] = fmaf(a.cz[j], (zr[RZ + v + j] + zr[RZ + v - j]) + m2c[v], lap[v]);
+        }
+        Vec<VZ> o;
+#pragma unroll
+        for (int v = 0; v < VZ; ++v) {
+            const float w = fmaf(P.be[v], c[v] - P.uo[v], c[v]);
+            o[v] = fmaf(P.al[v], lap[v], w);
+        }
+        if (a.inj_val) {
+            // planes without injected nodes skip the per-row lookup (uniform test)
+            const int32_t* rp = a.inj.row_ptr;
+            if (rp[(x + 1) * ny] != rp[x * ny] && own) {
+                const int64_t row = x * ny + y;
+                const int32_t e0 = rp[row], e1 = rp[row + 1];
+                float acc[VZ];
+                bool hit[VZ];
+#pragma unroll
+                for (int v = 0; v < VZ; ++v) { acc[v] = 0.f; hit[v] = false; }
+                for (int32_t e = e0; e < e1; ++e) {
+                    const InjEntry en = a.inj.ent[e];
+                    const int64_t dz = (int64_t)en.z - z;
+#pragma unroll
+                    for (int v = 0; v < VZ; ++v)
+                        if (dz == v) {
+                            acc[v] = fmaf(en.w, a.inj_val[en.pt], acc[v]);
+                            hit[v] = true;
+                        }
+                }
+#pragma unroll
+                for (int v = 0; v < VZ; ++v)
+                    if (hit[v]) o[v] = fmaf(P.al[v], acc[v], o[v]);
+            }
+        }
+        if (own) {
+            const int64_t off = x * sx + col;
+            if (IMG) {
+                const Vec<VZ> f = vload<VZ>(a.img_fwd + off);
+                Vec<VZ> g = vload<VZ>(a.img_grad + off);
+#pragma unroll
+                for (int v = 0; v < VZ; ++v) {
+                    const float d2 = (P.uo[v] + o[v]) + m2c[v];
+                    g[v] = fmaf(-f[v] * a.inv_dt2, d2, g[v]);
+                }
+                vstore<VZ>(a.img_grad + off, g);
+            }
+            vstore<VZ>(a.out + off, o);
+        }
+    };
+
+    for (int64_t x = xa; x < xb; x += S) {
+        bool go = true;
+        [&]<int... Us>(std::integer_sequence<int, Us...>) {
+            ((go = go && (x + Us < xb), go ? (plane(std::integral_constant<int, Us>{}, x + Us), 0) : 0), ...);
+        }(std::make_integer_sequence<int, S>{});
+    }
+}
+
 template <int DIM, int R>
-hipError_t launch_step_t(const StepArgs& a0, hipStream_t s)
+hipError_t launch_naive_t(const StepArgs& a0, hipStream_t s)
 {
     StepArgs a = a0;
     const int64_t n = a.nx * a.ny * a.nz;
@@ -126,18 +383,59 @@ hipError_t launch_step_t(const StepArgs& a0, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int DIM, int R, int VZ, int TZL, int TY>
+hipError_t launch_stream_t(const StepArgs& a0, hipStream_t s, int xchunk)
+{
+    using T = Tile<DIM, R, VZ, TZL, TY>;
+    StepArgs a = a0;
+    a.ntz = (int32_t)((a.nz + T::TZ - 1) / T::TZ);
+    a.nty = DIM == 3 ? (int32_t)((a.ny + TY - 1) / TY) : 1;
+    const int64_t tiles = (int64_t)a.ntz * a.nty;
+    if (xchunk <= 0) {
+        // about four blocks per CU on 256 CUs, but no chunk shorter than 4R planes
+        const int64_t want_chunks = (1024 + tiles - 1) / tiles;
+        int64_t xc = (a.nx + want_chunks - 1) / want_chunks;
+        if (xc < 4 * R) xc = 4 * R;
+        xchunk = (int)(xc < a.nx ? xc : a.nx);
+    }
+    a.xchunk = xchunk;
+    const int64_t nchunk = (a.nx + xchunk - 1) / xchunk;
+    a.stencil_blocks = tiles * nchunk;
+    a.remap = (a.stencil_blocks % 8 == 0) ? 1 : 0;
+    int64_t nsb = 0;
+    if (a.smp_out && a.smp.npts > 0) nsb = (a.smp.npts + T::NT - 1) / T::NT;
+    else a.smp.npts = 0;
+    const int64_t blocks = a.stencil_blocks + nsb;
+    if (a.img_grad)
+        hipLaunchKernelGGL((k_step_stream<DIM, R, VZ, TZL, TY, true>), dim3((unsigned)blocks),
+                           dim3(T::NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_step_stream<DIM, R, VZ, TZL, TY, false>), dim3((unsigned)blocks),
+                           dim3(T::NT), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int DIM, int R>
+hipError_t launch_r(const StepArgs& a, hipStream_t s, int kernel, int xchunk)
+{
+    if (kernel == kNaive) return launch_naive_t<DIM, R>(a, s);
+    if (DIM == 2) return launch_stream_t<2, R, 1, 256, 1>(a, s, xchunk);
+    if (a.nz % 4 == 0) return launch_stream_t<3, R, 4, 16, 16>(a, s, xchunk);
+    return launch_stream_t<3, R, 1, 64, 4>(a, s, xchunk);
+}
+
 template <int DIM>
-hipError_t launch_dim(int order, const StepArgs& a, hipStream_t s)
+hipError_t launch_dim(int order, const StepArgs& a, hipStream_t s, int kernel, int xchunk)
 {
     switch (order) {
-    case 2: return launch_step_t<DIM, 1>(a, s);
-    case 4: return launch_step_t<DIM, 2>(a, s);
-    case 6: return launch_step_t<DIM, 3>(a, s);
-    case 8: return launch_step_t<DIM, 4>(a, s);
-    case 10: return launch_step_t<DIM, 5>(a, s);
-    case 12: return launch_step_t<DIM, 6>(a, s);
-    case 14: return launch_step_t<DIM, 7>(a, s);
-    case 16: return launch_step_t<DIM, 8>(a, s);
+    case 2: return launch_r<DIM, 1>(a, s, kernel, xchunk);
+    case 4: return launch_r<DIM, 2>(a, s, kernel, xchunk);
+    case 6: return launch_r<DIM, 3>(a, s, kernel, xchunk);
+    case 8: return launch_r<DIM, 4>(a, s, kernel, xchunk);
+    case 10: return launch_r<DIM, 5>(a, s, kernel, xchunk);
+    case 12: return launch_r<DIM, 6>(a, s, kernel, xchunk);
+    case 14: return launch_r<DIM, 7>(a, s, kernel, xchunk);
+    case 16: return launch_r<DIM, 8>(a, s, kernel, xchunk);
     default: return hipErrorInvalidValue;
     }
 }
@@ -251,10 +549,11 @@ int grid_for(int64_t n)
 
 }  // namespace
 
-hipError_t launch_step(int ndim, int order, const StepArgs& a, hipStream_t s)
+hipError_t launch_step(int ndim, int order, const StepArgs& a, hipStream_t s, int kernel,
+                       int xchunk)
 {
-    if (ndim == 2) return launch_dim<2>(order, a, s);
-    if (ndim == 3) return launch_dim<3>(order, a, s);
+    if (ndim == 2) return launch_dim<2>(order, a, s, kernel, xchunk);
+    if (ndim == 3) return launch_dim<3>(order, a, s, kernel, xchunk);
     return hipErrorInvalidValue;
 }
 

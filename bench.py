@@ -49,6 +49,19 @@ def cpu_baseline(p, steps):
                       f"{p.nt} time steps, FP64, {el:.1f} s"}
 
 
+def copy_calibration():
+    """A plain device-to-device copy of 256 MiB, ten times: reads and writes
+    exactly 256 MiB each per launch, the reference for the HBM byte counters."""
+    import torch
+    n = 64 * 1024 * 1024
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(10):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": n * 4, "launches": 10}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,7 +70,15 @@ def main():
     ap.add_argument("--workload", default="3d-256-o8")
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--nt", type=int, default=0,
+                    help="override the number of time steps (for short profiler runs)")
+    ap.add_argument("--tile", type=int, default=0, help="x-chunk length (0 = automatic)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy 10 times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs on a single MI355X and has no "
               f"multi-GPU path (asked for --gpus {args.gpus})", file=sys.stderr)
@@ -68,6 +89,9 @@ def main():
 
     dev = torch.device("cuda:0")
     p = make_workload(args.workload)
+    if args.nt > 0:
+        p.nt = args.nt
+        p.q = p.q[: args.nt].copy()
     geom = api.Geometry(p.shape, p.spacing, p.order, p.dt, p.nt, p.src, p.rec)
     m = torch.from_numpy(p.m).to(dev)
     eta = torch.from_numpy(p.eta).to(dev)
@@ -76,7 +100,7 @@ def main():
           f"nrec {p.rec.shape[0]}", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
-        api.forward(geom, m, eta, q)
+        api.forward(geom, m, eta, q, tile=args.tile)
     torch.cuda.synchronize()
 
     _lib.set_profiling(True)
@@ -87,7 +111,7 @@ def main():
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(args.steps):
-        api.forward(geom, m, eta, q)
+        api.forward(geom, m, eta, q, tile=args.tile)
         ms, n = _lib.last_loop()          # waits for this run's loop to end
         loop_ms += ms
         launches += n

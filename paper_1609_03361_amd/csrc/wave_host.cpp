@@ -69,7 +69,7 @@ int prof_end(hipStream_t s)
 }
 
 constexpr size_t kAlign = 256;
-constexpr int kCheckBlocks = 512;
+constexpr int kCheckBlocks = 2048;
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -236,7 +236,8 @@ void make_inject(const Geo& G, const HostPoints& P, HostInject* out)
             out->ent.push_back(e);
         }
     }
-    std::stable_sort(out->ent.begin(), out->ent.end(), [](const InjEntry& a, const InjEntry& b) {
+    // (row, z, point) is a total order: two corners of one point never share a node
+    std::sort(out->ent.begin(), out->ent.end(), [](const InjEntry& a, const InjEntry& b) {
         if (a.row != b.row) return a.row < b.row;
         if (a.z != b.z) return a.z < b.z;
         return a.pt < b.pt;
@@ -293,14 +294,18 @@ Plan make_plan(int op, const Geo& G, int nsrc, int nrec, const wave_opts* o)
     P.alpha = c.take(N * 4);
     P.beta = c.take(N * 4);
     P.check = c.take((size_t)kCheckBlocks * 3 * 4);
-    const int npt[2] = {nrec, nsrc};
+    // sparse tables: the forward samples receivers and injects sources, the
+    // adjoint the other way round; the gradient needs both directions
+    const bool fwd = op != WAVE_OP_ADJOINT, adj = op != WAVE_OP_FORWARD;
+    const int npt[2] = {fwd ? nrec : 0, adj ? nsrc : 0};
     for (int s = 0; s < 2; ++s) {
         P.smp_base[s] = c.take((size_t)npt[s] * 8);
         P.smp_w[s] = c.take((size_t)npt[s] * nc * 4);
     }
-    const int ipt[2] = {nsrc, nrec};
+    const int ipt[2] = {fwd ? nsrc : 0, adj ? nrec : 0};
+    const bool iuse[2] = {fwd, adj};
     for (int s = 0; s < 2; ++s) {
-        P.inj_ptr[s] = c.take(((size_t)G.nrows() + 1) * 4);
+        P.inj_ptr[s] = c.take(iuse[s] ? ((size_t)G.nrows() + 1) * 4 : 0);
         P.inj_ent[s] = c.take((size_t)ipt[s] * nc * sizeof(InjEntry));
     }
     if (op == WAVE_OP_FORWARD || op == WAVE_OP_GRADIENT) {
@@ -366,7 +371,35 @@ void set_weights(Ctx& C)
     }
 }
 
-// Common set-up: tables, uploads, field validation (one wait), coefficients.
+// Pinned host staging for the per-call uploads (sparse tables) and the
+// validation read-back, one per thread, grown on demand.  An event marks the
+// last use so that a buffer is never rewritten while a copy reads it.  It is
+// deliberately not freed at thread exit (the runtime may already be gone).
+struct Staging {
+    char* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+};
+thread_local Staging g_stage;
+
+int staging(size_t bytes, char** out)
+{
+    if (g_stage.done) HIP_TRY(hipEventSynchronize(g_stage.done));
+    else HIP_TRY(hipEventCreateWithFlags(&g_stage.done, hipEventDisableTiming));
+    if (bytes > g_stage.cap) {
+        if (g_stage.host) HIP_TRY(hipHostFree(g_stage.host));
+        g_stage.host = nullptr;
+        g_stage.cap = 0;
+        const size_t cap = round_up(std::max<size_t>(bytes, 1 << 20), 1 << 20);
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&g_stage.host), cap, hipHostMallocDefault));
+        g_stage.cap = cap;
+    }
+    *out = g_stage.host;
+    return WAVE_OK;
+}
+
+// Common set-up: sparse tables, uploads, field validation and coefficients
+// (one pass over m and eta), then the only wait of the call.
 int setup(Ctx& C, int op, const wave_grid* grid, const float* m, const float* eta,
           const wave_points* src, const wave_points* rec, const wave_opts* o, void* stream)
 {
@@ -382,31 +415,44 @@ int setup(Ctx& C, int op, const wave_grid* grid, const float* m, const float* et
     C.xchunk = o->tile > 0 ? o->tile : 0;
     if (const char* k = std::getenv("WAVE_STEP_KERNEL")) C.kernel = std::strcmp(k, "naive") ? kStream : kNaive;
     set_weights(C);
-    make_inject(C.G, C.src, &C.inj_src);
-    make_inject(C.G, C.rec, &C.inj_rec);
+    const bool fwd = op != WAVE_OP_ADJOINT, adj = op != WAVE_OP_FORWARD;
+    if (fwd) make_inject(C.G, C.src, &C.inj_src);
+    if (adj) make_inject(C.G, C.rec, &C.inj_rec);
+
+    // gather every upload into the pinned staging buffer
+    struct Up { size_t dst; const void* src; size_t bytes; };
+    std::vector<Up> ups;
     const int nc = 1 << C.G.ndim;
-    const HostPoints* sp[2] = {&C.rec, &C.src};
+    const HostPoints* sp[2] = {fwd ? &C.rec : nullptr, adj ? &C.src : nullptr};
     for (int s = 0; s < 2; ++s) {
-        if (sp[s]->npts == 0) continue;
-        HIP_TRY(hipMemcpyAsync(C.at<void>(C.P.smp_base[s]), sp[s]->base.data(), sp[s]->npts * 8,
-                               hipMemcpyHostToDevice, C.s));
-        HIP_TRY(hipMemcpyAsync(C.at<void>(C.P.smp_w[s]), sp[s]->w.data(),
-                               (size_t)sp[s]->npts * nc * 4, hipMemcpyHostToDevice, C.s));
+        if (!sp[s] || sp[s]->npts == 0) continue;
+        ups.push_back({C.P.smp_base[s], sp[s]->base.data(), (size_t)sp[s]->npts * 8});
+        ups.push_back({C.P.smp_w[s], sp[s]->w.data(), (size_t)sp[s]->npts * nc * 4});
     }
-    const HostInject* ij[2] = {&C.inj_src, &C.inj_rec};
+    const HostInject* ij[2] = {fwd ? &C.inj_src : nullptr, adj ? &C.inj_rec : nullptr};
     for (int s = 0; s < 2; ++s) {
-        HIP_TRY(hipMemcpyAsync(C.at<void>(C.P.inj_ptr[s]), ij[s]->row_ptr.data(),
-                               ij[s]->row_ptr.size() * 4, hipMemcpyHostToDevice, C.s));
+        if (!ij[s]) continue;
+        ups.push_back({C.P.inj_ptr[s], ij[s]->row_ptr.data(), ij[s]->row_ptr.size() * 4});
         if (!ij[s]->ent.empty())
-            HIP_TRY(hipMemcpyAsync(C.at<void>(C.P.inj_ent[s]), ij[s]->ent.data(),
-                                   ij[s]->ent.size() * sizeof(InjEntry), hipMemcpyHostToDevice, C.s));
+            ups.push_back({C.P.inj_ent[s], ij[s]->ent.data(), ij[s]->ent.size() * sizeof(InjEntry)});
     }
-    // field validation + stability bound: the only wait of the call
+    const size_t part_bytes = (size_t)kCheckBlocks * 3 * 4;
+    size_t total = part_bytes;
+    for (const Up& u : ups) total += round_up(u.bytes, 64);
+    char* host = nullptr;
+    if ((rc = staging(total, &host))) return rc;
+    float* part = reinterpret_cast<float*>(host);
+    size_t off = part_bytes;
+    for (const Up& u : ups) {
+        std::memcpy(host + off, u.src, u.bytes);
+        HIP_TRY(hipMemcpyAsync(C.ws + u.dst, host + off, u.bytes, hipMemcpyHostToDevice, C.s));
+        off += round_up(u.bytes, 64);
+    }
     const int64_t N = C.G.npts();
-    HIP_TRY(launch_check_fields(m, eta, N, C.at<float>(C.P.check), kCheckBlocks, C.s));
-    std::vector<float> part((size_t)kCheckBlocks * 3);
-    HIP_TRY(hipMemcpyAsync(part.data(), C.at<float>(C.P.check), part.size() * 4,
-                           hipMemcpyDeviceToHost, C.s));
+    HIP_TRY(launch_check_fields(m, eta, N, C.at<float>(C.P.check), kCheckBlocks,
+                                C.at<float>(C.P.alpha), C.at<float>(C.P.beta), (float)C.G.dt, C.s));
+    HIP_TRY(hipMemcpyAsync(part, C.at<float>(C.P.check), part_bytes, hipMemcpyDeviceToHost, C.s));
+    HIP_TRY(hipEventRecord(g_stage.done, C.s));
     HIP_TRY(hipStreamSynchronize(C.s));
     float mmin = INFINITY, bad = 0;
     for (int b = 0; b < kCheckBlocks; ++b) {
@@ -420,8 +466,6 @@ int setup(Ctx& C, int op, const wave_grid* grid, const float* m, const float* et
     if (C.G.dt > dtmax)
         return fail(WAVE_ECFL, "dt = %.9g exceeds the stability bound %.9g (vmax = %.6g, order %d)",
                     C.G.dt, dtmax, vmax, C.G.order);
-    HIP_TRY(launch_coefficients(m, eta, C.at<float>(C.P.alpha), C.at<float>(C.P.beta), N,
-                                (float)C.G.dt, C.s));
     return WAVE_OK;
 }
 

@@ -69,12 +69,11 @@ enum StepKernel { kStream = 0, kNaive = 1 };
 // x-chunk length automatically.
 hipError_t launch_step(int ndim, int order, const StepArgs& a, hipStream_t s,
                        int kernel = kStream, int xchunk = 0);
-hipError_t launch_coefficients(const float* m, const float* eta, float* alpha, float* beta,
-                               int64_t n, float dt, hipStream_t s);
-// Partial reductions for validation: per block {min m, min eta (0 if eta null),
-// count of bad values}.  `partial` holds 3 * nblocks floats.
+// One pass over the model: per block {min m, min eta, count of invalid values}
+// into `partial` (3 * nblocks floats) for the host-side validation, and the
+// step coefficients alpha = dt^2/(m + eta dt/2), beta = (m - eta dt/2)/(m + eta dt/2).
 hipError_t launch_check_fields(const float* m, const float* eta, int64_t n, float* partial,
-                               int nblocks, hipStream_t s);
+                               int nblocks, float* alpha, float* beta, float dt, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
 // r = d - dobs over n values and misfit[0] = 1/2 sum r^2 (deterministic two-pass
 // reduction through `partial`, which holds nblocks floats).

@@ -143,6 +143,32 @@ __device__ __forceinline__ void vstore(float* p, const Vec<VZ>& v)
     *reinterpret_cast<Vec<VZ>*>(p) = v;
 }
 
+// Operands touched once per step (previous level, coefficients, output) are
+// streamed with the non-temporal hint so they do not evict the wavefield
+// planes that neighbouring tiles re-read as halos.
+#ifndef WAVE_STREAM_HINT
+#define WAVE_STREAM_HINT 1
+#endif
+template <int VZ>
+__device__ __forceinline__ Vec<VZ> vload_once(const float* p)
+{
+#if WAVE_STREAM_HINT
+    return __builtin_nontemporal_load(reinterpret_cast<const Vec<VZ>*>(p));
+#else
+    return *reinterpret_cast<const Vec<VZ>*>(p);
+#endif
+}
+
+template <int VZ>
+__device__ __forceinline__ void vstore_once(float* p, const Vec<VZ>& v)
+{
+#if WAVE_STREAM_HINT
+    __builtin_nontemporal_store(v, reinterpret_cast<Vec<VZ>*>(p));
+#else
+    *reinterpret_cast<Vec<VZ>*>(p) = v;
+#endif
+}
+
 // Wait for this wave's LDS traffic, then meet the block at the barrier.
 // Outstanding global loads stay in flight across it (no vmcnt wait).
 __device__ __forceinline__ void lds_barrier()
@@ -163,8 +189,12 @@ struct Tile {
     static constexpr int S = 2 * R + 2;                     // queue slots
 };
 
+#ifndef WAVE_MIN_WAVES
+#define WAVE_MIN_WAVES 1
+#endif
 template <int DIM, int R, int VZ, int TZL, int TY, bool IMG>
-__global__ __launch_bounds__(TZL* TY) void k_step_stream(StepArgs a)
+__global__ __launch_bounds__(TZL* TY) __attribute__((amdgpu_waves_per_eu(WAVE_MIN_WAVES, 8)))
+void k_step_stream(StepArgs a)
 {
     using T = Tile<DIM, R, VZ, TZL, TY>;
     constexpr int NT = T::NT, TZ = T::TZ, RZ = T::RZ, PITCH = T::PITCH, S = T::S, KH = T::KH;
@@ -244,9 +274,9 @@ __global__ __launch_bounds__(TZL* TY) void k_step_stream(StepArgs a)
         }
         P.uo = P.al = P.be = vzero<VZ>();
         if (own) {
-            P.uo = vload<VZ>(a.other + xx * sx + col);
-            P.al = vload<VZ>(a.alpha + xx * sx + col);
-            P.be = vload<VZ>(a.beta + xx * sx + col);
+            P.uo = vload_once<VZ>(a.other + xx * sx + col);
+            P.al = vload_once<VZ>(a.alpha + xx * sx + col);
+            P.be = vload_once<VZ>(a.beta + xx * sx + col);
         }
     };
     if (xa < xb) fetch(pre0, xa);
@@ -354,7 +384,7 @@ __global__ __launch_bounds__(TZL* TY) void k_step_stream(StepArgs a)
                 }
                 vstore<VZ>(a.img_grad + off, g);
             }
-            vstore<VZ>(a.out + off, o);
+            vstore_once<VZ>(a.out + off, o);
         }
     };
 
@@ -392,10 +422,11 @@ hipError_t launch_stream_t(const StepArgs& a0, hipStream_t s, int xchunk)
     a.nty = DIM == 3 ? (int32_t)((a.ny + TY - 1) / TY) : 1;
     const int64_t tiles = (int64_t)a.ntz * a.nty;
     if (xchunk <= 0) {
-        // about four blocks per CU on 256 CUs, but no chunk shorter than 4R planes
-        const int64_t want_chunks = (1024 + tiles - 1) / tiles;
+        // about eight blocks per CU on 256 CUs (two residency rounds), so that
+        // enough loads are in flight, but no chunk shorter than 2R planes
+        const int64_t want_chunks = (2048 + tiles - 1) / tiles;
         int64_t xc = (a.nx + want_chunks - 1) / want_chunks;
-        if (xc < 4 * R) xc = 4 * R;
+        if (xc < 2 * R) xc = 2 * R;
         xchunk = (int)(xc < a.nx ? xc : a.nx);
     }
     a.xchunk = xchunk;
@@ -420,7 +451,10 @@ hipError_t launch_r(const StepArgs& a, hipStream_t s, int kernel, int xchunk)
 {
     if (kernel == kNaive) return launch_naive_t<DIM, R>(a, s);
     if (DIM == 2) return launch_stream_t<2, R, 1, 256, 1>(a, s, xchunk);
-    if (a.nz % 4 == 0) return launch_stream_t<3, R, 4, 16, 16>(a, s, xchunk);
+#ifndef WAVE_TILE_Y3
+#define WAVE_TILE_Y3 16
+#endif
+    if (a.nz % 4 == 0) return launch_stream_t<3, R, 4, 16, WAVE_TILE_Y3>(a, s, xchunk);
     return launch_stream_t<3, R, 1, 64, 4>(a, s, xchunk);
 }
 
@@ -440,39 +474,33 @@ hipError_t launch_dim(int order, const StepArgs& a, hipStream_t s, int kernel, i
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_coefficients(const float* __restrict__ m,
-                                                         const float* __restrict__ eta,
-                                                         float* __restrict__ alpha,
-                                                         float* __restrict__ beta, int64_t n,
-                                                         float dt)
-{
-    const float hdt = 0.5f * dt, dt2 = dt * dt;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
-        const float mm = m[i];
-        const float e = eta ? eta[i] * hdt : 0.f;
-        const float a = mm + e;
-        alpha[i] = dt2 / a;
-        beta[i] = (mm - e) / a;
-    }
-}
-
+// One pass over m and eta: validity counts and min(m) per block for the
+// host-side checks, and the step coefficients
+//   alpha = dt^2 / (m + eta dt/2),  beta = (m - eta dt/2) / (m + eta dt/2).
 __global__ __launch_bounds__(kBlock) void k_check_fields(const float* __restrict__ m,
                                                          const float* __restrict__ eta,
-                                                         int64_t n, float* __restrict__ partial)
+                                                         int64_t n, float* __restrict__ partial,
+                                                         float* __restrict__ alpha,
+                                                         float* __restrict__ beta, float dt)
 {
     __shared__ float smin_m[kBlock], smin_e[kBlock], sbad[kBlock];
     float mn = INFINITY, en = INFINITY, bad = 0.f;
+    const float hdt = 0.5f * dt, dt2 = dt * dt;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock) {
         const float mm = m[i];
         if (!(mm > 0.f) || !isfinite(mm)) bad += 1.f;
         else mn = fminf(mn, mm);
+        float e = 0.f;
         if (eta) {
-            const float e = eta[i];
+            e = eta[i];
             if (!(e >= 0.f) || !isfinite(e)) bad += 1.f;
             else en = fminf(en, e);
+            e *= hdt;
         }
+        const float am = mm + e;
+        alpha[i] = dt2 / am;
+        beta[i] = (mm - e) / am;
     }
     smin_m[threadIdx.x] = mn;
     smin_e[threadIdx.x] = en;
@@ -557,18 +585,11 @@ hipError_t launch_step(int ndim, int order, const StepArgs& a, hipStream_t s, in
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_coefficients(const float* m, const float* eta, float* alpha, float* beta,
-                               int64_t n, float dt, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_coefficients, dim3(grid_for(n)), dim3(kBlock), 0, s, m, eta, alpha,
-                       beta, n, dt);
-    return hipGetLastError();
-}
-
 hipError_t launch_check_fields(const float* m, const float* eta, int64_t n, float* partial,
-                               int nblocks, hipStream_t s)
+                               int nblocks, float* alpha, float* beta, float dt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_check_fields, dim3(nblocks), dim3(kBlock), 0, s, m, eta, n, partial);
+    hipLaunchKernelGGL(k_check_fields, dim3(nblocks), dim3(kBlock), 0, s, m, eta, n, partial,
+                       alpha, beta, dt);
     return hipGetLastError();
 }
 

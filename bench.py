@@ -62,6 +62,44 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_per_launch": n * 4, "launches": 10}), flush=True)
 
 
+def gradient_bench(dev, reps=2):
+    """FWI gradient on the 200^3 order-8 workload (1500 steps, 4 shots,
+    checkpoints every 20 steps): seconds per shot of the checkpointed
+    gradient (FP32 / BF16 / FP16 snapshots) against the plain forward."""
+    import torch
+    from paper_1609_03361_amd import api, synth
+    m0, m_true, eta, shots = synth.config_gradient_3d()
+    m = torch.from_numpy(m0).to(dev)
+    mt = torch.from_numpy(m_true).to(dev)
+    e = torch.from_numpy(eta).to(dev)
+    geoms = [api.Geometry(p.shape, p.spacing, p.order, p.dt, p.nt, p.src, p.rec) for p in shots]
+    qs = [torch.from_numpy(p.q).to(dev) for p in shots]
+    dobs = [api.forward(g, mt, e, q) for g, q in zip(geoms, qs)]
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best / len(shots)
+
+    fwd = timed(lambda: [api.forward(g, m, e, q) for g, q in zip(geoms, qs)])
+    out = {"workload": f"3d-{shots[0].shape[0]}-o{shots[0].order}, {shots[0].nt} steps, "
+                       f"{len(shots)} shots, {shots[0].rec.shape[0]} receivers, checkpoint every 20",
+           "forward_s_per_shot": round(fwd, 5)}
+    for dt in ("fp32", "bf16", "fp16"):
+        s = timed(lambda: [api.gradient(g, m, e, q, d, ckpt_every=20, ckpt_dtype=dt)
+                           for g, q, d in zip(geoms, qs, dobs)])
+        out[f"gradient_{dt}_s_per_shot"] = round(s, 5)
+        out[f"gradient_{dt}_vs_forward"] = round(s / fwd, 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +108,8 @@ def main():
     ap.add_argument("--workload", default="3d-256-o8")
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gradient", action="store_true",
+                    help="skip the FWI-gradient seconds-per-shot measurement")
     ap.add_argument("--nt", type=int, default=0,
                     help="override the number of time steps (for short profiler runs)")
     ap.add_argument("--tile", type=int, default=0, help="x-chunk length (0 = automatic)")
@@ -147,6 +187,8 @@ def main():
                      "kernel": "leapfrog step", "launch_ms": round(per_launch_ms, 5),
                      "alg_bytes_per_launch": alg_bytes},
     }
+    if not args.no_gradient:
+        out["fwi_gradient"] = gradient_bench(dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
     print(json.dumps(out), flush=True)

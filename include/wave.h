@@ -101,8 +101,13 @@ typedef enum {
 int wave_workspace_size(int32_t op, const wave_grid* grid, const wave_points* src,
                         const wave_points* rec, const wave_opts* opts, size_t* bytes);
 
-/* Bytes of checkpoint storage for opts->ckpt_every / opts->ckpt_dtype:
- * one (u^c, u^{c-1}) pair per segment, plus one FP32 scale per snapshot. */
+/* Bytes of checkpoint storage for opts->ckpt_every / opts->ckpt_dtype.  One
+ * checkpoint per segment of ckpt_every steps: FP32 keeps the pair (u^c,
+ * u^{c-1}) exactly, so the backward replay is bitwise the forward run; BF16
+ * and FP16 keep u^c and the increment u^c - u^{c-1}, each scaled by its own
+ * power of two (largest magnitude mapped into [2^14, 2^15)) and rounded to
+ * nearest even, so the replayed velocity carries one rounding of the
+ * increment rather than of two nearly equal states. */
 int wave_checkpoint_size(const wave_grid* grid, const wave_opts* opts, size_t* bytes);
 
 /*

@@ -282,7 +282,7 @@ size_t ckpt_bytes(const Geo& G, const wave_opts* o)
     const int K = ckpt_every(o);
     const int64_t nck = (G.nt + K - 1) / K;
     const size_t snap = round_up((size_t)G.npts() * ckpt_elem(o), kAlign);
-    return (size_t)nck * 2 * snap + round_up((size_t)nck * 2 * sizeof(float), kAlign);
+    return (size_t)nck * 2 * snap + round_up((size_t)nck * 4 * sizeof(float), kAlign);
 }
 
 Plan make_plan(int op, const Geo& G, int nsrc, int nrec, const wave_opts* o)
@@ -502,14 +502,17 @@ hipError_t step(const Ctx& C, const StepArgs& a)
     return launch_step(C.G.ndim, C.G.order, a, C.s, C.kernel, C.xchunk);
 }
 
+// Checkpoint storage: per checkpoint c two snapshot arrays (FP32: u^c and
+// u^{c-1}; BF16/FP16: u^c and u^c - u^{c-1}, scaled) and a 4-word slot with
+// the two scales.
 struct CkptView {
     char* base = nullptr;
-    int K = 20, elem = 4, nck = 0;
+    int K = 20, elem = 4, nck = 0, dtype = WAVE_CKPT_FP32;
     size_t snap = 0;
     void* snapshot(int c, int which) const { return base + ((size_t)c * 2 + which) * snap; }
-    float* scale(int c, int which) const
+    unsigned int* slot(int c) const
     {
-        return reinterpret_cast<float*>(base + (size_t)nck * 2 * snap) + (size_t)c * 2 + which;
+        return reinterpret_cast<unsigned int*>(base + (size_t)nck * 2 * snap) + (size_t)c * 4;
     }
 };
 
@@ -519,29 +522,38 @@ CkptView ckpt_view(const Geo& G, const wave_opts* o, void* base)
     v.base = static_cast<char*>(base);
     v.K = ckpt_every(o);
     v.elem = ckpt_elem(o);
+    v.dtype = o ? o->ckpt_dtype : WAVE_CKPT_FP32;
     v.nck = (G.nt + v.K - 1) / v.K;
     v.snap = round_up((size_t)G.npts() * v.elem, kAlign);
     return v;
 }
 
-int store_snapshot(const Ctx& C, const CkptView& v, int c, int which, const float* u)
+int store_checkpoint(const Ctx& C, const CkptView& v, int c, const float* cur, const float* prev)
 {
-    if (v.elem == 4) {
-        HIP_TRY(hipMemcpyAsync(v.snapshot(c, which), u, (size_t)C.G.npts() * 4,
-                               hipMemcpyDeviceToDevice, C.s));
+    const int64_t N = C.G.npts();
+    if (v.dtype == WAVE_CKPT_FP32) {
+        HIP_TRY(hipMemcpyAsync(v.snapshot(c, 0), cur, (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
+        HIP_TRY(hipMemcpyAsync(v.snapshot(c, 1), prev, (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
         return WAVE_OK;
     }
-    return fail(WAVE_EINVAL, "reduced-precision checkpoints are not available yet");
+    HIP_TRY(launch_ckpt_encode(cur, prev, N, v.dtype == WAVE_CKPT_BF16, v.slot(c),
+                               static_cast<unsigned short*>(v.snapshot(c, 0)),
+                               static_cast<unsigned short*>(v.snapshot(c, 1)), C.s));
+    return WAVE_OK;
 }
 
-int load_snapshot(const Ctx& C, const CkptView& v, int c, int which, float* u)
+int load_checkpoint(const Ctx& C, const CkptView& v, int c, float* cur, float* prev)
 {
-    if (v.elem == 4) {
-        HIP_TRY(hipMemcpyAsync(u, v.snapshot(c, which), (size_t)C.G.npts() * 4,
-                               hipMemcpyDeviceToDevice, C.s));
+    const int64_t N = C.G.npts();
+    if (v.dtype == WAVE_CKPT_FP32) {
+        HIP_TRY(hipMemcpyAsync(cur, v.snapshot(c, 0), (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
+        HIP_TRY(hipMemcpyAsync(prev, v.snapshot(c, 1), (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
         return WAVE_OK;
     }
-    return fail(WAVE_EINVAL, "reduced-precision checkpoints are not available yet");
+    HIP_TRY(launch_ckpt_decode(static_cast<const unsigned short*>(v.snapshot(c, 0)),
+                               static_cast<const unsigned short*>(v.snapshot(c, 1)), v.slot(c), N,
+                               v.dtype == WAVE_CKPT_BF16, cur, prev, C.s));
+    return WAVE_OK;
 }
 
 // Forward time loop over the two-buffer in-place leapfrog.  If `ck` is set,
@@ -559,8 +571,7 @@ int run_forward(const Ctx& C, const float* q, float* d, float* u_final, const Ck
     if (prof_begin(C.s)) return fail(WAVE_EHIP, "profiling event failed");
     for (int n = 0; n < C.G.nt; ++n) {
         if (ck && n % ck->K == 0) {
-            int rc = store_snapshot(C, *ck, n / ck->K, 0, buf[cur]);
-            if (!rc) rc = store_snapshot(C, *ck, n / ck->K, 1, buf[1 - cur]);
+            const int rc = store_checkpoint(C, *ck, n / ck->K, buf[cur], buf[1 - cur]);
             if (rc) return rc;
         }
         a.cur = buf[cur];
@@ -603,8 +614,7 @@ int run_backward(const Ctx& C, const float* q, const float* r, const CkptView& c
         const int c0 = seg * ck.K;
         const int c1 = std::min(c0 + ck.K, nt);
         // ring slot i holds u^{c0 - 1 + i}
-        int rc = load_snapshot(C, ck, seg, 1, slot(0));
-        if (!rc) rc = load_snapshot(C, ck, seg, 0, slot(1));
+        const int rc = load_checkpoint(C, ck, seg, slot(1), slot(0));
         if (rc) return rc;
         for (int n = c0; n < c1 - 1; ++n) {
             fa.cur = slot(n - c0 + 1);

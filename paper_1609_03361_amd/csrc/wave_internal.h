@@ -75,6 +75,15 @@ hipError_t launch_step(int ndim, int order, const StepArgs& a, hipStream_t s,
 hipError_t launch_check_fields(const float* m, const float* eta, int64_t n, float* partial,
                                int nblocks, float* alpha, float* beta, float dt, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
+// Reduced-precision checkpoint of (cur, prev): stores cur and cur - prev as
+// BF16 (bf16 != 0) or FP16 with per-array power-of-two scales kept in `slot`
+// (4 words: scale_u, scale_d, and two reduction words).
+hipError_t launch_ckpt_encode(const float* cur, const float* prev, int64_t n, int bf16,
+                              unsigned int* slot, unsigned short* out_u, unsigned short* out_d,
+                              hipStream_t s);
+hipError_t launch_ckpt_decode(const unsigned short* in_u, const unsigned short* in_d,
+                              const unsigned int* slot, int64_t n, int bf16, float* cur, float* prev,
+                              hipStream_t s);
 // r = d - dobs over n values and misfit[0] = 1/2 sum r^2 (deterministic two-pass
 // reduction through `partial`, which holds nblocks floats).
 hipError_t launch_residual(const float* d, const float* dobs, float* r, int64_t n, float* partial,

@@ -13,6 +13,8 @@
 // sampling needs no ordering with the update.
 #include "wave_internal.h"
 
+#include <hip/hip_fp16.h>
+
 #include <utility>
 
 namespace wave {
@@ -567,6 +569,108 @@ __global__ __launch_bounds__(kBlock) void k_sum_half(const float* __restrict__ p
     if (threadIdx.x == 0) *out = 0.5f * sh[0];
 }
 
+// ---------------------------------------------------------------------------
+// Checkpoint codec.  A reduced-precision checkpoint of the pair (u^c, u^{c-1})
+// stores u^c and the increment d = u^c - u^{c-1}, each as BF16 or FP16 of
+// (value * s) with its own power-of-two scale s, chosen so that max|value| * s
+// lies in [2^14, 2^15): the products are exact and FP16 cannot overflow.
+// Restoring gives u^c = stored_u / s_u and u^{c-1} = u^c - stored_d / s_d, so
+// the restart velocity carries the relative error of one rounding of d.
+// slot layout per checkpoint: {s_u, s_d, max|u| bits, max|d| bits}.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned short f32_to_bf16_rn(float x)
+{
+    unsigned int b = __float_as_uint(x);
+    if ((b & 0x7f800000u) == 0x7f800000u) return (unsigned short)((b >> 16) | ((b & 0xffffu) ? 0x40u : 0u));
+    b += 0x7fffu + ((b >> 16) & 1u);
+    return (unsigned short)(b >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+__device__ __forceinline__ float scale_for(unsigned int maxbits)
+{
+    const float mx = __uint_as_float(maxbits);
+    if (!(mx > 0.f) || !isfinite(mx)) return 1.f;
+    int k;
+    (void)frexpf(mx, &k);          // mx = f 2^k, f in [0.5, 1)
+    int e = 15 - k;                // mx 2^e in [2^14, 2^15)
+    e = e < -120 ? -120 : (e > 120 ? 120 : e);
+    return ldexpf(1.f, e);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ckpt_max(const float* __restrict__ cur,
+                                                     const float* __restrict__ prev, int64_t n,
+                                                     unsigned int* __restrict__ slot)
+{
+    __shared__ float sa[kBlock], sd[kBlock];
+    float ma = 0.f, md = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const float c = cur[i];
+        ma = fmaxf(ma, fabsf(c));
+        md = fmaxf(md, fabsf(c - prev[i]));
+    }
+    sa[threadIdx.x] = ma;
+    sd[threadIdx.x] = md;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sa[threadIdx.x] = fmaxf(sa[threadIdx.x], sa[threadIdx.x + w]);
+            sd[threadIdx.x] = fmaxf(sd[threadIdx.x], sd[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMax(slot + 2, __float_as_uint(sa[0]));
+        atomicMax(slot + 3, __float_as_uint(sd[0]));
+    }
+}
+
+template <bool BF16>
+__global__ __launch_bounds__(kBlock) void k_ckpt_encode(const float* __restrict__ cur,
+                                                        const float* __restrict__ prev, int64_t n,
+                                                        unsigned int* __restrict__ slot,
+                                                        unsigned short* __restrict__ out_u,
+                                                        unsigned short* __restrict__ out_d)
+{
+    const float su = scale_for(slot[2]), sd = scale_for(slot[3]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        reinterpret_cast<float*>(slot)[0] = su;
+        reinterpret_cast<float*>(slot)[1] = sd;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const float c = cur[i];
+        const float d = c - prev[i];
+        if (BF16) {
+            out_u[i] = f32_to_bf16_rn(c * su);
+            out_d[i] = f32_to_bf16_rn(d * sd);
+        } else {
+            out_u[i] = __half_as_ushort(__float2half_rn(c * su));
+            out_d[i] = __half_as_ushort(__float2half_rn(d * sd));
+        }
+    }
+}
+
+template <bool BF16>
+__global__ __launch_bounds__(kBlock) void k_ckpt_decode(const unsigned short* __restrict__ in_u,
+                                                        const unsigned short* __restrict__ in_d,
+                                                        const float* __restrict__ slot, int64_t n,
+                                                        float* __restrict__ cur,
+                                                        float* __restrict__ prev)
+{
+    const float iu = 1.f / slot[0], id = 1.f / slot[1];   // exact: powers of two
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const float u = BF16 ? bf16_to_f32(in_u[i]) : __half2float(__ushort_as_half(in_u[i]));
+        const float d = BF16 ? bf16_to_f32(in_d[i]) : __half2float(__ushort_as_half(in_d[i]));
+        const float c = u * iu;
+        cur[i] = c;
+        prev[i] = c - d * id;
+    }
+}
+
 int grid_for(int64_t n)
 {
     int64_t b = (n + kBlock - 1) / kBlock;
@@ -600,6 +704,38 @@ hipError_t launch_residual(const float* d, const float* dobs, float* r, int64_t 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum_half, dim3(1), dim3(kBlock), 0, s, partial, nblocks, misfit);
+    return hipGetLastError();
+}
+
+hipError_t launch_ckpt_encode(const float* cur, const float* prev, int64_t n, int bf16,
+                              unsigned int* slot, unsigned short* out_u, unsigned short* out_d,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, reinterpret_cast<float*>(slot), 4, 0.f);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ckpt_max, dim3(grid_for(n)), dim3(kBlock), 0, s, cur, prev, n, slot);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (bf16)
+        hipLaunchKernelGGL(k_ckpt_encode<true>, dim3(grid_for(n)), dim3(kBlock), 0, s, cur, prev, n,
+                           slot, out_u, out_d);
+    else
+        hipLaunchKernelGGL(k_ckpt_encode<false>, dim3(grid_for(n)), dim3(kBlock), 0, s, cur, prev,
+                           n, slot, out_u, out_d);
+    return hipGetLastError();
+}
+
+hipError_t launch_ckpt_decode(const unsigned short* in_u, const unsigned short* in_d,
+                              const unsigned int* slot, int64_t n, int bf16, float* cur, float* prev,
+                              hipStream_t s)
+{
+    const float* sl = reinterpret_cast<const float*>(slot);
+    if (bf16)
+        hipLaunchKernelGGL(k_ckpt_decode<true>, dim3(grid_for(n)), dim3(kBlock), 0, s, in_u, in_d,
+                           sl, n, cur, prev);
+    else
+        hipLaunchKernelGGL(k_ckpt_decode<false>, dim3(grid_for(n)), dim3(kBlock), 0, s, in_u, in_d,
+                           sl, n, cur, prev);
     return hipGetLastError();
 }
 

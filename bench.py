@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -100,6 +102,54 @@ def gradient_bench(dev, reps=2):
     return out
 
 
+def batched_bench(dev, reps=2):
+    """48 2D shots of uneven aperture on a 2001 x 801 layered model, order 8,
+    2000 steps, one launch per step over all shots replayed from a hipGraph,
+    tile chosen by the autotuner; against the single-shot order-8 2D kernel
+    on the full 2001 x 801 model."""
+    import torch
+    from paper_1609_03361_amd import api, synth
+    probs = synth.config_batched_2d()
+    shots = []
+    for p in probs:
+        geom = api.Geometry(p.shape, p.spacing, p.order, p.dt, p.nt, p.src, p.rec)
+        shots.append((geom, torch.from_numpy(p.m).to(dev), torch.from_numpy(p.eta).to(dev),
+                      torch.from_numpy(p.q).to(dev)))
+    tile, tune_us = api.tune_batch(shots, steps=10)
+    pts = sum(p.npoints for p in probs) * probs[0].nt
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best
+
+    tb = timed(lambda: api.forward_batch(shots, tile=tile))
+    # the same model as one shot, through the single-shot path
+    m_full, _ = synth.layered((2001, 801), 4)
+    vmax = float(np.max(1.0 / np.sqrt(m_full.astype(np.float64))))
+    eta_full = synth.sponge(m_full, 10.0, 40, vmax)
+    p0 = probs[0]
+    geom = api.Geometry(m_full.shape, p0.spacing, p0.order, p0.dt, p0.nt,
+                        np.array([[1000 * 10.0, 25.0]]), synth.line_receivers(400, 20000.0, 20.0))
+    mf = torch.from_numpy(m_full).to(dev)
+    ef = torch.from_numpy(eta_full).to(dev)
+    ts = timed(lambda: api.forward(geom, mf, ef, shots[0][3]))
+    single = m_full.size * p0.nt / ts / 1e9
+    batched = pts / tb / 1e9
+    return {"workload": f"{len(probs)} 2D shots, widths {min(p.shape[0] for p in probs)}-"
+                        f"{max(p.shape[0] for p in probs)} x 801, order 8, {p0.nt} steps",
+            "batched_gpts": round(batched, 2), "batched_s": round(tb, 4),
+            "tile": {"variant": tile >> 16, "xchunk": tile & 0xffff, "tuned_us_per_step": round(tune_us, 2)},
+            "single_shot_full_model_gpts": round(single, 2),
+            "batched_vs_single": round(batched / single, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +160,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gradient", action="store_true",
                     help="skip the FWI-gradient seconds-per-shot measurement")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched multi-shot measurement")
     ap.add_argument("--nt", type=int, default=0,
                     help="override the number of time steps (for short profiler runs)")
     ap.add_argument("--tile", type=int, default=0, help="x-chunk length (0 = automatic)")
@@ -189,6 +241,8 @@ def main():
     }
     if not args.no_gradient:
         out["fwi_gradient"] = gradient_bench(dev)
+    if not args.no_batched:
+        out["batched_shots"] = batched_bench(dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
     print(json.dumps(out), flush=True)

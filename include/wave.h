@@ -85,9 +85,12 @@ typedef struct {
     size_t workspace_bytes;
     int32_t ckpt_every;       /* gradient/checkpointing: steps per segment, 0 = 20 */
     int32_t ckpt_dtype;       /* wave_ckpt_dtype for stored snapshots */
-    int32_t tile;             /* 0 = automatic, > 0 = x-chunk length (planes per block) */
-    int32_t flags;            /* reserved, set to 0 */
+    int32_t tile;             /* 0 = tuned if wave_tune has seen this grid, else automatic;
+                                 > 0 = explicit tile id (variant << 16 | x-chunk planes) */
+    int32_t flags;            /* WAVE_FLAG_* bits */
 } wave_opts;
+
+#define WAVE_FLAG_NO_GRAPH 1  /* batch: launch the steps one by one instead of replaying a hipGraph */
 
 typedef enum {
     WAVE_OP_FORWARD = 0,      /* wave_forward (no checkpoints) */
@@ -173,6 +176,47 @@ int wave_gradient(const wave_grid* grid, const float* m, const float* eta,
                   const wave_points* rec, const float* d_obs,
                   float* grad, float* misfit, float* d_syn,
                   const wave_opts* opts, void* stream);
+
+/*
+ * Many shots at once (the paper's remark that an inversion workflow runs many
+ * operators in parallel, Section "Discussion"): every shot is forward
+ * modelled exactly as by wave_forward, but step n of all shots runs in one
+ * launch over a flattened list of (shot, tile, x-chunk) blocks, and the nt
+ * launches are captured once into a hipGraph that is replayed (and reused by
+ * later calls with the same buffers).  Shots may differ in shape, spacing,
+ * fields and points; they must share ndim, space_order, nt and dt (3D: also
+ * whether nz is a multiple of 4).  Each shot's results are bitwise those of
+ * wave_forward on the same shot.
+ */
+typedef struct {
+    wave_grid grid;
+    const float* m;           /* [shape] */
+    const float* eta;         /* [shape] or NULL */
+    wave_points src;
+    const float* q;           /* [nt][nsrc] */
+    wave_points rec;
+    float* d;                 /* [nt][nrec], written */
+    float* u_final;           /* NULL or [shape]: receives u^nt */
+} wave_shot;
+
+int wave_batch_workspace_size(int32_t nshots, const wave_shot* shots, const wave_opts* opts,
+                              size_t* bytes);
+int wave_forward_batch(int32_t nshots, const wave_shot* shots, const wave_opts* opts, void* stream);
+
+/*
+ * Tile autotuner (the paper's brute-force search over loop-blocking sizes,
+ * Section "Loop Blocking"): times every candidate tile of the step kernel
+ * (block shape x x-chunk length) for `steps` launches on this grid (or batch)
+ * using the workspace (size of WAVE_OP_FORWARD, resp. the batch), keeps the
+ * fastest in a process-wide cache that calls with opts->tile == 0 consult
+ * (mirrored to the file named by the environment variable WAVE_TUNE_CACHE),
+ * and returns its id and its time per step in microseconds.  Candidates give
+ * bitwise identical results; no output buffer is written.
+ */
+int wave_tune(const wave_grid* grid, const wave_opts* opts, int32_t steps, void* stream,
+              int32_t* tile, double* us_per_step);
+int wave_tune_batch(int32_t nshots, const wave_shot* shots, const wave_opts* opts, int32_t steps,
+                    void* stream, int32_t* tile, double* us_per_step);
 
 /* Phase timing (a metrics aid).  With profiling on, each entry point called
  * by this thread records HIP events on its stream around its time loop(s),

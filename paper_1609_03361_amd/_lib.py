@@ -21,8 +21,10 @@ _NAMES = {0: "WAVE_OK", -1: "WAVE_EINVAL", -2: "WAVE_ECFL", -3: "WAVE_ERANGE",
           -4: "WAVE_EWORKSPACE", -5: "WAVE_EHIP"}
 
 EXPORTS = ["wave_workspace_size", "wave_checkpoint_size", "wave_forward", "wave_adjoint",
-           "wave_backward", "wave_gradient", "wave_set_profiling", "wave_last_loop",
+           "wave_backward", "wave_gradient", "wave_batch_workspace_size", "wave_forward_batch",
+           "wave_tune", "wave_tune_batch", "wave_set_profiling", "wave_last_loop",
            "wave_last_error", "wave_version"]
+WAVE_FLAG_NO_GRAPH = 1
 
 
 class WaveError(RuntimeError):
@@ -47,6 +49,11 @@ class Opts(C.Structure):
                 ("flags", C.c_int32)]
 
 
+class Shot(C.Structure):
+    _fields_ = [("grid", Grid), ("m", C.c_void_p), ("eta", C.c_void_p), ("src", Points),
+                ("q", C.c_void_p), ("rec", Points), ("d", C.c_void_p), ("u_final", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -68,8 +75,13 @@ def lib():
                                     P(Opts), VP]
         L.wave_gradient.argtypes = [P(Grid), VP, VP, P(Points), VP, P(Points), VP, VP, VP, VP,
                                     P(Opts), VP]
+        L.wave_batch_workspace_size.argtypes = [I32, P(Shot), P(Opts), P(C.c_size_t)]
+        L.wave_forward_batch.argtypes = [I32, P(Shot), P(Opts), VP]
+        L.wave_tune.argtypes = [P(Grid), P(Opts), I32, VP, P(C.c_int32), P(C.c_double)]
+        L.wave_tune_batch.argtypes = [I32, P(Shot), P(Opts), I32, VP, P(C.c_int32), P(C.c_double)]
         for name in ("wave_workspace_size", "wave_checkpoint_size", "wave_forward", "wave_adjoint",
-                     "wave_backward", "wave_gradient"):
+                     "wave_backward", "wave_gradient", "wave_batch_workspace_size",
+                     "wave_forward_batch", "wave_tune", "wave_tune_batch"):
             getattr(L, name).restype = C.c_int
         L.wave_set_profiling.argtypes = [I32]
         L.wave_set_profiling.restype = C.c_int
@@ -117,14 +129,15 @@ class HostPoints:
         return self.arr.shape[0]
 
 
-def make_opts(workspace_ptr=0, workspace_bytes=0, ckpt_every=0, ckpt_dtype="fp32", tile=0) -> Opts:
+def make_opts(workspace_ptr=0, workspace_bytes=0, ckpt_every=0, ckpt_dtype="fp32", tile=0,
+              flags=0) -> Opts:
     o = Opts()
     o.workspace = workspace_ptr or None
     o.workspace_bytes = int(workspace_bytes)
     o.ckpt_every = int(ckpt_every)
     o.ckpt_dtype = CKPT_DTYPES[ckpt_dtype] if isinstance(ckpt_dtype, str) else int(ckpt_dtype)
     o.tile = int(tile)
-    o.flags = 0
+    o.flags = int(flags)
     return o
 
 

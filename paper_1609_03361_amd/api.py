@@ -20,7 +20,7 @@ import torch
 from . import _lib as L
 
 __all__ = ["Geometry", "forward", "adjoint", "backward", "gradient", "checkpoint_bytes",
-           "WaveFn", "wave_apply"]
+           "forward_batch", "tune", "tune_batch", "WaveFn", "wave_apply"]
 
 
 def _ptr(t):
@@ -157,6 +157,85 @@ def gradient(geom: Geometry, m, eta, q, d_obs, ckpt_every=0, ckpt_dtype="fp32",
                                   C.byref(rp.s), _ptr(d_obs), _ptr(g), _ptr(J), _ptr(dsyn),
                                   C.byref(o), _stream(dev)), "wave_gradient")
     return (J, g, dsyn) if return_data else (J, g)
+
+
+def tile_id(variant: int, xchunk: int) -> int:
+    """Public tile id of the streaming kernel: block-shape variant and x-chunk length."""
+    return (int(variant) << 16) | int(xchunk)
+
+
+def tune(geom: Geometry, steps: int = 20, device=None):
+    """Time every candidate tile on this grid; returns (tile id, us per step).
+    The winner is cached for later calls with tile=0."""
+    dev = torch.device(device or "cuda:0")
+    grid = geom.grid()
+    empty = L.HostPoints(None, len(geom.shape))
+    ws, o = _workspace(L.WAVE_OP_FORWARD, grid, empty, empty, {}, dev)
+    t = C.c_int32(0)
+    us = C.c_double(0)
+    L.check(L.lib().wave_tune(C.byref(grid), C.byref(o), int(steps), _stream(dev), C.byref(t),
+                              C.byref(us)), "wave_tune")
+    return int(t.value), float(us.value)
+
+
+class _Batch:
+    """Marshals a list of (geometry, m, eta, q) into wave_shot structs."""
+
+    def __init__(self, shots, return_final):
+        self.keep = []
+        n = len(shots)
+        self.arr = (L.Shot * n)()
+        self.d, self.uf = [], []
+        for i, (geom, m, eta, q) in enumerate(shots):
+            _need(m, f"shot {i} m", geom.shape)
+            _need(eta, f"shot {i} eta", geom.shape)
+            sp, rp = geom.points()
+            if sp.npts:
+                _need(q, f"shot {i} q", (geom.nt, sp.npts))
+            d = torch.empty((geom.nt, rp.npts), dtype=torch.float32, device=m.device)
+            uf = torch.empty(geom.shape, dtype=torch.float32, device=m.device) if return_final else None
+            s = self.arr[i]
+            s.grid = geom.grid()
+            s.m, s.eta, s.q = _ptr(m), _ptr(eta), _ptr(q)
+            s.src, s.rec = sp.s, rp.s
+            s.d = _ptr(d) if rp.npts else None
+            s.u_final = _ptr(uf)
+            self.keep += [sp, rp, m, eta, q]
+            self.d.append(d)
+            self.uf.append(uf)
+        self.n = n
+        self.dev = shots[0][1].device
+
+    def workspace(self, **kw):
+        nbytes = C.c_size_t(0)
+        o = L.make_opts(**kw)
+        L.check(L.lib().wave_batch_workspace_size(self.n, self.arr, C.byref(o), C.byref(nbytes)),
+                "wave_batch_workspace_size")
+        buf = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.dev)
+        off = (-buf.data_ptr()) % 256
+        return buf, L.make_opts(buf.data_ptr() + off, int(nbytes.value), **kw)
+
+
+def forward_batch(shots, return_final=False, tile=0, graph=True):
+    """Forward-model many shots in one launch per step (captured in a hipGraph).
+    ``shots``: list of (Geometry, m, eta, q).  Returns the list of traces (and
+    of final wavefields if ``return_final``)."""
+    B = _Batch(shots, return_final)
+    ws, o = B.workspace(tile=tile, flags=0 if graph else L.WAVE_FLAG_NO_GRAPH)
+    L.check(L.lib().wave_forward_batch(B.n, B.arr, C.byref(o), _stream(B.dev)),
+            "wave_forward_batch")
+    return (B.d, B.uf) if return_final else B.d
+
+
+def tune_batch(shots, steps: int = 10):
+    """Tile autotuner for a batch; returns (tile id, us per step)."""
+    B = _Batch(shots, False)
+    ws, o = B.workspace()
+    t = C.c_int32(0)
+    us = C.c_double(0)
+    L.check(L.lib().wave_tune_batch(B.n, B.arr, C.byref(o), int(steps), _stream(B.dev),
+                                    C.byref(t), C.byref(us)), "wave_tune_batch")
+    return int(t.value), float(us.value)
 
 
 class WaveFn(torch.autograd.Function):

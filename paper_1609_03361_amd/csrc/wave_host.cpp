@@ -10,6 +10,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <exception>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -330,6 +332,58 @@ Plan make_plan(int op, const Geo& G, int nsrc, int nrec, const wave_opts* o)
 }
 
 // ---------------------------------------------------------------------------
+// Tile cache: the fastest tile found by wave_tune / wave_tune_batch for a
+// grid, consulted when opts->tile == 0.  Process-wide; mirrored to the file
+// named by WAVE_TUNE_CACHE (lines "key tile_id") when that is set.
+// ---------------------------------------------------------------------------
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("WAVE_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char key[256];
+    int id;
+    while (std::fscanf(f, "%255s %d", key, &id) == 2) g_tune[key] = id;
+    std::fclose(f);
+}
+
+std::string tune_key(const Geo& G)
+{
+    char b[128];
+    std::snprintf(b, sizeof b, "d%do%d:%lldx%lldx%lld", G.ndim, G.order, (long long)G.n[0],
+                  (long long)G.n[1], (long long)G.n[2]);
+    return b;
+}
+
+TileCfg cached_tile(const std::string& key)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(key);
+    return it == g_tune.end() ? TileCfg{} : tile_from_id(it->second);
+}
+
+void store_tile(const std::string& key, int id)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    g_tune[key] = id;
+    if (const char* path = std::getenv("WAVE_TUNE_CACHE")) {
+        if (FILE* f = std::fopen(path, "a")) {
+            std::fprintf(f, "%s %d\n", key.c_str(), id);
+            std::fclose(f);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Per-call device context
 // ---------------------------------------------------------------------------
 struct Ctx {
@@ -341,7 +395,7 @@ struct Ctx {
     HostPoints rec, src;
     HostInject inj_src, inj_rec;
     int kernel = kStream;   // step kernel variant
-    int xchunk = 0;         // x-chunk length of the streaming kernel (0 = automatic)
+    TileCfg cfg;            // block shape and x-chunk of the streaming kernel
     template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
 
@@ -412,7 +466,7 @@ int setup(Ctx& C, int op, const wave_grid* grid, const float* m, const float* et
     if ((rc = check_ws(C.P, o))) return rc;
     C.ws = static_cast<char*>(o->workspace);
     C.s = static_cast<hipStream_t>(stream);
-    C.xchunk = o->tile > 0 ? o->tile : 0;
+    C.cfg = o->tile > 0 ? tile_from_id(o->tile) : cached_tile(tune_key(C.G));
     if (const char* k = std::getenv("WAVE_STEP_KERNEL")) C.kernel = std::strcmp(k, "naive") ? kStream : kNaive;
     set_weights(C);
     const bool fwd = op != WAVE_OP_ADJOINT, adj = op != WAVE_OP_FORWARD;
@@ -499,7 +553,7 @@ void bind_sparse(const Ctx& C, StepArgs& a, int set)
 hipError_t step(const Ctx& C, const StepArgs& a)
 {
     ++g_prof.launches;
-    return launch_step(C.G.ndim, C.G.order, a, C.s, C.kernel, C.xchunk);
+    return launch_step(C.G.ndim, C.G.order, a, C.s, C.kernel, C.cfg);
 }
 
 // Checkpoint storage: per checkpoint c two snapshot arrays (FP32: u^c and
@@ -636,6 +690,303 @@ int run_backward(const Ctx& C, const float* q, const float* r, const CkptView& c
     }
     if (prof_end(C.s)) return fail(WAVE_EHIP, "profiling event failed");
     HIP_TRY(hipMemcpyAsync(grad, gacc, (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
+    return WAVE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tile autotuner (the paper's brute-force search over block sizes, Section
+// "Loop Blocking", applied to the streaming kernel's block shape and x-chunk):
+// each candidate is launched `steps` times on zeroed workspace buffers and
+// timed with HIP events; the fastest per-step time wins.  Timing does not
+// depend on the field values, and every candidate gives bitwise the same
+// result (the per-point arithmetic does not depend on the tiling).
+// ---------------------------------------------------------------------------
+std::vector<TileCfg> tile_candidates(int ndim, int half, int64_t nx, int64_t nz)
+{
+    std::vector<TileCfg> out;
+    const int xs[] = {2 * half, 4 * half, 8, 16, 32, 64, 128};
+    for (int v = 0; v < tile_variants(ndim, nz); ++v)
+        for (int x : xs) {
+            if (x > nx && x != 2 * half) continue;
+            TileCfg c;
+            c.variant = v;
+            c.xchunk = (int)std::min<int64_t>(x, nx);
+            bool dup = false;
+            for (const TileCfg& o : out) dup = dup || (o.variant == c.variant && o.xchunk == c.xchunk);
+            if (!dup) out.push_back(c);
+        }
+    return out;
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Batched shots: every shot's step n runs in one launch over a flattened list
+// of (shot, tile, x-chunk) blocks; the nt launches are captured once into a
+// hipGraph (on a library-owned capture stream) and replayed on the caller's
+// stream.  The instantiated graph is kept per thread and reused while the
+// launch arguments are unchanged.
+// ---------------------------------------------------------------------------
+struct BatchShot {
+    Geo G;
+    HostPoints rec, src;
+    HostInject inj;
+    size_t alpha = 0, beta = 0, buf0 = 0, buf1 = 0, smp_base = 0, smp_w = 0, inj_ptr = 0, inj_ent = 0;
+};
+
+struct BatchPlan {
+    std::vector<BatchShot> shots;
+    size_t desc = 0, begin = 0, check = 0, total = 0;
+};
+
+constexpr int kCheckBlocksShot = 256;
+
+int batch_plan(int32_t nshots, const wave_shot* shots, BatchPlan* B, bool build_tables)
+{
+    if (nshots < 1 || !shots) return fail(WAVE_EINVAL, "need at least one shot");
+    B->shots.assign(nshots, BatchShot{});
+    Carver c;
+    B->desc = c.take(sizeof(ShotDesc) * (size_t)nshots);
+    B->begin = c.take(sizeof(int64_t) * ((size_t)nshots + 1));
+    B->check = c.take((size_t)nshots * kCheckBlocksShot * 3 * 4);
+    for (int i = 0; i < nshots; ++i) {
+        BatchShot& S = B->shots[i];
+        int rc = make_geo(&shots[i].grid, &S.G);
+        if (rc) return fail(rc, "shot %d: %s", i, g_error.c_str());
+        const Geo& G0 = B->shots[0].G;
+        if (S.G.ndim != G0.ndim || S.G.order != G0.order || S.G.nt != G0.nt || S.G.dt != G0.dt)
+            return fail(WAVE_EINVAL, "shot %d: every shot needs the same ndim, space_order, nt and dt", i);
+        if (S.G.ndim == 3 && (S.G.n[2] % 4 == 0) != (G0.n[2] % 4 == 0))
+            return fail(WAVE_EINVAL, "shot %d: 3D shots must all have nz %% 4 == 0 or all not", i);
+        if (!shots[i].m) return fail(WAVE_EINVAL, "shot %d: m is NULL", i);
+        if (shots[i].src.npts > 0 && !shots[i].q) return fail(WAVE_EINVAL, "shot %d: q is NULL", i);
+        if (shots[i].rec.npts > 0 && !shots[i].d) return fail(WAVE_EINVAL, "shot %d: d is NULL", i);
+        if (build_tables) {
+            if ((rc = make_points(S.G, &shots[i].rec, "receiver", &S.rec)))
+                return fail(rc, "shot %d: %s", i, g_error.c_str());
+            if ((rc = make_points(S.G, &shots[i].src, "source", &S.src)))
+                return fail(rc, "shot %d: %s", i, g_error.c_str());
+        }
+        const int ns = shots[i].src.npts > 0 ? shots[i].src.npts : 0;
+        const int nr = shots[i].rec.npts > 0 ? shots[i].rec.npts : 0;
+        const size_t N = (size_t)S.G.npts();
+        const int nc = 1 << S.G.ndim;
+        S.alpha = c.take(N * 4);
+        S.beta = c.take(N * 4);
+        S.buf0 = c.take(N * 4);
+        S.buf1 = c.take(N * 4);
+        S.smp_base = c.take((size_t)nr * 8);
+        S.smp_w = c.take((size_t)nr * nc * 4);
+        S.inj_ptr = c.take(((size_t)S.G.nrows() + 1) * 4);
+        S.inj_ent = c.take((size_t)ns * nc * sizeof(InjEntry));
+    }
+    B->total = c.off;
+    return WAVE_OK;
+}
+
+StepArgs shot_args(const BatchShot& S, char* ws)
+{
+    StepArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.alpha = reinterpret_cast<float*>(ws + S.alpha);
+    a.beta = reinterpret_cast<float*>(ws + S.beta);
+    a.nx = S.G.n[0]; a.ny = S.G.n[1]; a.nz = S.G.n[2];
+    double c[kMaxHalf + 1];
+    fd_weights(S.G.half, c);
+    for (int j = 1; j <= S.G.half; ++j) {
+        a.cx[j] = (float)(c[j] / (S.G.h[0] * S.G.h[0]));
+        a.cy[j] = S.G.ndim == 3 ? (float)(c[j] / (S.G.h[1] * S.G.h[1])) : 0.f;
+        a.cz[j] = (float)(c[j] / (S.G.h[2] * S.G.h[2]));
+    }
+    a.inv_dt2 = (float)(1.0 / (S.G.dt * S.G.dt));
+    a.inj.row_ptr = reinterpret_cast<int32_t*>(ws + S.inj_ptr);
+    a.inj.ent = reinterpret_cast<InjEntry*>(ws + S.inj_ent);
+    a.smp.base = reinterpret_cast<int64_t*>(ws + S.smp_base);
+    a.smp.w = reinterpret_cast<float*>(ws + S.smp_w);
+    a.smp.npts = S.rec.npts;
+    return a;
+}
+
+// Descriptors for a tile config; returns the total block count via *blocks.
+void build_descs(const BatchPlan& B, const wave_shot* shots, char* ws, TileCfg cfg,
+                 std::vector<ShotDesc>* desc, std::vector<int64_t>* begin, int64_t* blocks)
+{
+    const int n = (int)B.shots.size();
+    desc->assign(n, ShotDesc{});
+    begin->assign(n + 1, 0);
+    int64_t acc = 0;
+    for (int i = 0; i < n; ++i) {
+        const BatchShot& S = B.shots[i];
+        ShotDesc& D = (*desc)[i];
+        D.a = shot_args(S, ws);
+        D.a.smp_out = S.rec.npts ? shots[i].d : nullptr;   // marks sampling as active for planning
+        const int64_t nb = plan_tiles(S.G.ndim, S.G.order, cfg, D.a);
+        D.a.smp_out = nullptr;
+        D.buf[0] = reinterpret_cast<float*>(ws + S.buf0);
+        D.buf[1] = reinterpret_cast<float*>(ws + S.buf1);
+        D.q = shots[i].q;
+        D.d = S.rec.npts ? shots[i].d : nullptr;
+        D.nsrc = S.src.npts;
+        D.nrec = S.rec.npts;
+        (*begin)[i] = acc;
+        acc += nb;
+    }
+    (*begin)[n] = acc;
+    *blocks = acc;
+}
+
+// Uploads, field checks (one wait for all shots), coefficient fields and
+// zeroed wavefields.
+int batch_setup(const BatchPlan& B, const wave_shot* shots, char* ws, hipStream_t st)
+{
+    const int n = (int)B.shots.size();
+    struct Up { size_t dst; const void* src; size_t bytes; };
+    std::vector<Up> ups;
+    std::vector<HostInject> injs(n);
+    const int nc = 1 << B.shots[0].G.ndim;
+    for (int i = 0; i < n; ++i) {
+        const BatchShot& S = B.shots[i];
+        make_inject(S.G, S.src, &injs[i]);
+        if (S.rec.npts) {
+            ups.push_back({S.smp_base, S.rec.base.data(), (size_t)S.rec.npts * 8});
+            ups.push_back({S.smp_w, S.rec.w.data(), (size_t)S.rec.npts * nc * 4});
+        }
+        ups.push_back({S.inj_ptr, injs[i].row_ptr.data(), injs[i].row_ptr.size() * 4});
+        if (!injs[i].ent.empty())
+            ups.push_back({S.inj_ent, injs[i].ent.data(), injs[i].ent.size() * sizeof(InjEntry)});
+    }
+    const size_t part_bytes = (size_t)n * kCheckBlocksShot * 3 * 4;
+    size_t total = part_bytes;
+    for (const Up& u : ups) total += round_up(u.bytes, 64);
+    char* host = nullptr;
+    int rc = staging(total, &host);
+    if (rc) return rc;
+    size_t off = part_bytes;
+    for (const Up& u : ups) {
+        std::memcpy(host + off, u.src, u.bytes);
+        HIP_TRY(hipMemcpyAsync(ws + u.dst, host + off, u.bytes, hipMemcpyHostToDevice, st));
+        off += round_up(u.bytes, 64);
+    }
+    float* part = reinterpret_cast<float*>(host);
+    for (int i = 0; i < n; ++i) {
+        const BatchShot& S = B.shots[i];
+        HIP_TRY(launch_check_fields(shots[i].m, shots[i].eta, S.G.npts(),
+                                    reinterpret_cast<float*>(ws + B.check) + (size_t)i * kCheckBlocksShot * 3,
+                                    kCheckBlocksShot, reinterpret_cast<float*>(ws + S.alpha),
+                                    reinterpret_cast<float*>(ws + S.beta), (float)S.G.dt, st));
+    }
+    HIP_TRY(hipMemcpyAsync(part, ws + B.check, part_bytes, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(g_stage.done, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) {
+        const BatchShot& S = B.shots[i];
+        float mmin = INFINITY, bad = 0;
+        for (int b = 0; b < kCheckBlocksShot; ++b) {
+            mmin = std::min(mmin, part[((size_t)i * kCheckBlocksShot + b) * 3]);
+            bad += part[((size_t)i * kCheckBlocksShot + b) * 3 + 2];
+        }
+        if (bad > 0) return fail(WAVE_EINVAL, "shot %d: %.0f invalid entries in m/eta", i, bad);
+        const double dtmax = cfl_dt_max(S.G, 1.0 / std::sqrt((double)mmin));
+        if (S.G.dt > dtmax)
+            return fail(WAVE_ECFL, "shot %d: dt = %.9g exceeds the stability bound %.9g", i, S.G.dt, dtmax);
+    }
+    for (int i = 0; i < n; ++i) {
+        const BatchShot& S = B.shots[i];
+        HIP_TRY(launch_fill(reinterpret_cast<float*>(ws + S.buf0), S.G.npts(), 0.f, st));
+        HIP_TRY(launch_fill(reinterpret_cast<float*>(ws + S.buf1), S.G.npts(), 0.f, st));
+    }
+    return WAVE_OK;
+}
+
+int upload_descs(const std::vector<ShotDesc>& desc, const std::vector<int64_t>& begin, char* ws,
+                 const BatchPlan& B, hipStream_t st)
+{
+    const size_t db = desc.size() * sizeof(ShotDesc), bb = begin.size() * sizeof(int64_t);
+    char* host = nullptr;
+    int rc = staging(db + bb, &host);
+    if (rc) return rc;
+    std::memcpy(host, desc.data(), db);
+    std::memcpy(host + db, begin.data(), bb);
+    HIP_TRY(hipMemcpyAsync(ws + B.desc, host, db, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ws + B.begin, host + db, bb, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(g_stage.done, st));
+    return WAVE_OK;
+}
+
+std::string batch_key(const BatchPlan& B)
+{
+    int64_t pts = 0, mx = 0;
+    for (const BatchShot& S : B.shots) { pts += S.G.npts(); mx = std::max(mx, S.G.n[0]); }
+    char b[160];
+    const Geo& G = B.shots[0].G;
+    std::snprintf(b, sizeof b, "batch:d%do%d:%zu:%lld:%lldx%lld", G.ndim, G.order, B.shots.size(),
+                  (long long)pts, (long long)mx, (long long)G.n[2]);
+    return b;
+}
+
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    hipStream_t capture = nullptr;
+    std::vector<char> key;
+};
+thread_local GraphCache g_graph;
+
+int run_batch_loop(const BatchPlan& B, char* ws, TileCfg cfg, int64_t blocks, hipStream_t st,
+                   bool use_graph)
+{
+    const Geo& G = B.shots[0].G;
+    const int nshots = (int)B.shots.size();
+    const ShotDesc* d_desc = reinterpret_cast<const ShotDesc*>(ws + B.desc);
+    const int64_t* d_begin = reinterpret_cast<const int64_t*>(ws + B.begin);
+    if (!use_graph) {
+        for (int n = 0; n < G.nt; ++n) {
+            ++g_prof.launches;
+            HIP_TRY(launch_batch(G.ndim, G.order, G.n[2], cfg, d_desc, d_begin, nshots, blocks, n, st));
+        }
+        return WAVE_OK;
+    }
+    // graph identity: everything the captured launches bake in
+    std::vector<char> key(sizeof(void*) * 2 + sizeof(int64_t) * 2 + sizeof(int) * 6);
+    {
+        char* k = key.data();
+        auto put = [&](const void* p, size_t n) { std::memcpy(k, p, n); k += n; };
+        put(&d_desc, sizeof(void*)); put(&d_begin, sizeof(void*));
+        put(&blocks, sizeof(int64_t)); int64_t nz = G.n[2]; put(&nz, sizeof(int64_t));
+        int v[6] = {nshots, G.nt, G.ndim, G.order, cfg.variant, cfg.xchunk};
+        put(v, sizeof v);
+    }
+    if (!g_graph.exec || g_graph.key != key) {
+        if (g_graph.exec) { HIP_TRY(hipGraphExecDestroy(g_graph.exec)); g_graph.exec = nullptr; }
+        if (!g_graph.capture) HIP_TRY(hipStreamCreateWithFlags(&g_graph.capture, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(g_graph.capture, hipStreamCaptureModeThreadLocal));
+        hipError_t err = hipSuccess;
+        for (int n = 0; n < G.nt && err == hipSuccess; ++n)
+            err = launch_batch(G.ndim, G.order, G.n[2], cfg, d_desc, d_begin, nshots, blocks, n,
+                               g_graph.capture);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(g_graph.capture, &graph);
+        if (err != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(WAVE_EHIP, "graph capture of the batched loop failed: %s",
+                        hipGetErrorString(err != hipSuccess ? err : e2));
+        }
+        const hipError_t e3 = hipGraphInstantiate(&g_graph.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e3 != hipSuccess) {
+            g_graph.exec = nullptr;
+            return fail(WAVE_EHIP, "graph instantiation failed: %s", hipGetErrorString(e3));
+        }
+        g_graph.key = key;
+    }
+    g_prof.launches += G.nt;
+    HIP_TRY(hipGraphLaunch(g_graph.exec, st));
     return WAVE_OK;
 }
 
@@ -798,6 +1149,170 @@ int wave_gradient(const wave_grid* grid, const float* m, const float* eta, const
         float* resid = C.at<float>(C.P.resid);
         HIP_TRY(launch_residual(dsyn, d_obs, resid, nd, C.at<float>(C.P.red), 1024, misfit, C.s));
         return run_backward(C, q, resid, ck, grad, nullptr, false);
+    } catch (const std::exception& e) {
+        return fail(WAVE_EINVAL, "exception: %s", e.what());
+    } catch (...) {
+        return fail(WAVE_EINVAL, "unknown exception");
+    }
+}
+
+
+int wave_batch_workspace_size(int32_t nshots, const wave_shot* shots, const wave_opts* opts,
+                              size_t* bytes)
+{
+    try {
+        (void)opts;
+        if (!bytes) return fail(WAVE_EINVAL, "bytes is NULL");
+        BatchPlan B;
+        const int rc = batch_plan(nshots, shots, &B, false);
+        if (rc) return rc;
+        *bytes = B.total;
+        return WAVE_OK;
+    } catch (const std::exception& e) {
+        return fail(WAVE_EINVAL, "exception: %s", e.what());
+    } catch (...) {
+        return fail(WAVE_EINVAL, "unknown exception");
+    }
+}
+
+int wave_forward_batch(int32_t nshots, const wave_shot* shots, const wave_opts* opts, void* stream)
+{
+    try {
+        BatchPlan B;
+        int rc = batch_plan(nshots, shots, &B, true);
+        if (rc) return rc;
+        if (!opts || !opts->workspace || reinterpret_cast<uintptr_t>(opts->workspace) % kAlign)
+            return fail(WAVE_EWORKSPACE, "workspace missing or not %zu-byte aligned", kAlign);
+        if (opts->workspace_bytes < B.total)
+            return fail(WAVE_EWORKSPACE, "workspace too small: %zu bytes given, %zu needed",
+                        opts->workspace_bytes, B.total);
+        char* ws = static_cast<char*>(opts->workspace);
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if ((rc = batch_setup(B, shots, ws, st))) return rc;
+        const TileCfg cfg = opts->tile > 0 ? tile_from_id(opts->tile) : cached_tile(batch_key(B));
+        std::vector<ShotDesc> desc;
+        std::vector<int64_t> begin;
+        int64_t blocks = 0;
+        build_descs(B, shots, ws, cfg, &desc, &begin, &blocks);
+        if ((rc = upload_descs(desc, begin, ws, B, st))) return rc;
+        if (prof_begin(st)) return fail(WAVE_EHIP, "profiling event failed");
+        rc = run_batch_loop(B, ws, cfg, blocks, st, !(opts->flags & WAVE_FLAG_NO_GRAPH));
+        if (rc) return rc;
+        if (prof_end(st)) return fail(WAVE_EHIP, "profiling event failed");
+        const int last = B.shots[0].G.nt & 1;
+        for (int i = 0; i < nshots; ++i)
+            if (shots[i].u_final) {
+                const BatchShot& S = B.shots[i];
+                HIP_TRY(hipMemcpyAsync(shots[i].u_final, ws + (last ? S.buf1 : S.buf0),
+                                       (size_t)S.G.npts() * 4, hipMemcpyDeviceToDevice, st));
+            }
+        return WAVE_OK;
+    } catch (const std::exception& e) {
+        return fail(WAVE_EINVAL, "exception: %s", e.what());
+    } catch (...) {
+        return fail(WAVE_EINVAL, "unknown exception");
+    }
+}
+
+int wave_tune(const wave_grid* grid, const wave_opts* opts, int32_t steps, void* stream,
+              int32_t* tile, double* us_per_step)
+{
+    try {
+        Ctx C;
+        if (!tile || !us_per_step || steps < 1) return fail(WAVE_EINVAL, "tile, us_per_step and steps >= 1 are required");
+        int rc = make_geo(grid, &C.G);
+        if (rc) return rc;
+        C.P = make_plan(WAVE_OP_FORWARD, C.G, 0, 0, opts);
+        if ((rc = check_ws(C.P, opts))) return rc;
+        C.ws = static_cast<char*>(opts->workspace);
+        C.s = static_cast<hipStream_t>(stream);
+        set_weights(C);
+        const int64_t N = C.G.npts();
+        for (size_t off : {C.P.alpha, C.P.beta, C.P.wf[0], C.P.wf[1]})
+            HIP_TRY(launch_fill(C.at<float>(off), N, 0.f, C.s));
+        StepArgs a = base_args(C);
+        a.cur = C.at<float>(C.P.wf[0]);
+        a.other = a.out = C.at<float>(C.P.wf[1]);
+        EventPair ev;
+        HIP_TRY(hipEventCreate(&ev.a));
+        HIP_TRY(hipEventCreate(&ev.b));
+        double best = 1e300;
+        TileCfg best_cfg;
+        for (const TileCfg& cfg : tile_candidates(C.G.ndim, C.G.half, C.G.n[0], C.G.n[2])) {
+            for (int w = 0; w < 2; ++w) HIP_TRY(launch_step(C.G.ndim, C.G.order, a, C.s, kStream, cfg));
+            double t = 1e300;
+            for (int rep = 0; rep < 3; ++rep) {
+                HIP_TRY(hipEventRecord(ev.a, C.s));
+                for (int i = 0; i < steps; ++i) HIP_TRY(launch_step(C.G.ndim, C.G.order, a, C.s, kStream, cfg));
+                HIP_TRY(hipEventRecord(ev.b, C.s));
+                HIP_TRY(hipEventSynchronize(ev.b));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
+                t = std::min(t, 1e3 * ms / steps);
+            }
+            if (t < best) { best = t; best_cfg = cfg; }
+        }
+        *tile = tile_id(best_cfg);
+        *us_per_step = best;
+        store_tile(tune_key(C.G), *tile);
+        return WAVE_OK;
+    } catch (const std::exception& e) {
+        return fail(WAVE_EINVAL, "exception: %s", e.what());
+    } catch (...) {
+        return fail(WAVE_EINVAL, "unknown exception");
+    }
+}
+
+int wave_tune_batch(int32_t nshots, const wave_shot* shots, const wave_opts* opts, int32_t steps,
+                    void* stream, int32_t* tile, double* us_per_step)
+{
+    try {
+        if (!tile || !us_per_step || steps < 1) return fail(WAVE_EINVAL, "tile, us_per_step and steps >= 1 are required");
+        BatchPlan B;
+        int rc = batch_plan(nshots, shots, &B, true);
+        if (rc) return rc;
+        if (!opts || !opts->workspace || reinterpret_cast<uintptr_t>(opts->workspace) % kAlign ||
+            opts->workspace_bytes < B.total)
+            return fail(WAVE_EWORKSPACE, "workspace missing, misaligned or too small");
+        char* ws = static_cast<char*>(opts->workspace);
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if ((rc = batch_setup(B, shots, ws, st))) return rc;
+        const Geo& G = B.shots[0].G;
+        int64_t maxnx = 0;
+        for (const BatchShot& S : B.shots) maxnx = std::max(maxnx, S.G.n[0]);
+        EventPair ev;
+        HIP_TRY(hipEventCreate(&ev.a));
+        HIP_TRY(hipEventCreate(&ev.b));
+        double best = 1e300;
+        TileCfg best_cfg;
+        const ShotDesc* d_desc = reinterpret_cast<const ShotDesc*>(ws + B.desc);
+        const int64_t* d_begin = reinterpret_cast<const int64_t*>(ws + B.begin);
+        for (const TileCfg& cfg : tile_candidates(G.ndim, G.half, maxnx, G.n[2])) {
+            std::vector<ShotDesc> desc;
+            std::vector<int64_t> begin;
+            int64_t blocks = 0;
+            build_descs(B, shots, ws, cfg, &desc, &begin, &blocks);
+            for (ShotDesc& D : desc) { D.nsrc = 0; D.nrec = 0; D.d = nullptr; }   // no outputs touched
+            if ((rc = upload_descs(desc, begin, ws, B, st))) return rc;
+            for (int w = 0; w < 2; ++w)
+                HIP_TRY(launch_batch(G.ndim, G.order, G.n[2], cfg, d_desc, d_begin, nshots, blocks, w, st));
+            double t = 1e300;
+            for (int rep = 0; rep < 3; ++rep) {
+                HIP_TRY(hipEventRecord(ev.a, st));
+                for (int i = 0; i < steps; ++i)
+                    HIP_TRY(launch_batch(G.ndim, G.order, G.n[2], cfg, d_desc, d_begin, nshots, blocks, i, st));
+                HIP_TRY(hipEventRecord(ev.b, st));
+                HIP_TRY(hipEventSynchronize(ev.b));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
+                t = std::min(t, 1e3 * ms / steps);
+            }
+            if (t < best) { best = t; best_cfg = cfg; }
+        }
+        *tile = tile_id(best_cfg);
+        *us_per_step = best;
+        store_tile(batch_key(B), *tile);
+        return WAVE_OK;
     } catch (const std::exception& e) {
         return fail(WAVE_EINVAL, "exception: %s", e.what());
     } catch (...) {

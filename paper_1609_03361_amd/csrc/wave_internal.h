@@ -61,14 +61,44 @@ struct StepArgs {
     float inv_dt2;
 };
 
+// One shot of a batched launch: the static step arguments plus the base
+// pointers that the step index selects from.
+struct ShotDesc {
+    StepArgs a;          // cur/other/out/inj_val/smp_out are set per step
+    float* buf[2];       // wavefield pair: even steps read buf[0], odd steps buf[1]
+    const float* q;      // [nt][nsrc]
+    float* d;            // [nt][nrec] or nullptr
+    int32_t nsrc, nrec;
+};
+
 // Kernel variants of the time step.  kStream: 2.5D register-streaming along
 // x with (y, z) planes staged in LDS; kNaive: one thread per point.
 enum StepKernel { kStream = 0, kNaive = 1 };
 
-// Launchers (return hipError_t of the launch).  `xchunk` <= 0 picks the
-// x-chunk length automatically.
-hipError_t launch_step(int ndim, int order, const StepArgs& a, hipStream_t s,
-                       int kernel = kStream, int xchunk = 0);
+// Tile configuration of the streaming kernel: block shape variant and x-chunk
+// length (0 = chosen from the grid).  Public tile id: (variant << 16) | xchunk.
+struct TileCfg {
+    int variant = 0;
+    int xchunk = 0;
+};
+inline TileCfg tile_from_id(int id) { TileCfg c; c.variant = (id >> 16) & 0xff; c.xchunk = id & 0xffff; return c; }
+inline int tile_id(const TileCfg& c) { return (c.variant << 16) | c.xchunk; }
+
+// Number of block-shape variants for a grid (2D: 3; 3D with nz % 4 == 0: 2; else 1).
+int tile_variants(int ndim, int64_t nz);
+// Fill the tiling fields of `a` (ntz, nty, xchunk, stencil_blocks, remap) for
+// `cfg`; returns the block count of one launch including receiver samplers.
+int64_t plan_tiles(int ndim, int order, TileCfg cfg, StepArgs& a);
+
+// Launchers (return hipError_t of the launch).  `a` must have been planned
+// with the same cfg unless kernel == kNaive.
+hipError_t launch_step(int ndim, int order, const StepArgs& a, hipStream_t s, int kernel,
+                       TileCfg cfg);
+// One step of every shot in one launch; every shot must be planned with the
+// same cfg; `begin` holds the first block of each shot and the total.
+hipError_t launch_batch(int ndim, int order, int64_t nz_any, TileCfg cfg, const ShotDesc* shots,
+                        const int64_t* begin, int32_t nshots, int64_t blocks, int32_t n,
+                        hipStream_t s);
 // One pass over the model: per block {min m, min eta, count of invalid values}
 // into `partial` (3 * nblocks floats) for the host-side validation, and the
 // step coefficients alpha = dt^2/(m + eta dt/2), beta = (m - eta dt/2)/(m + eta dt/2).

@@ -191,12 +191,10 @@ struct Tile {
     static constexpr int S = 2 * R + 2;                     // queue slots
 };
 
-#ifndef WAVE_MIN_WAVES
-#define WAVE_MIN_WAVES 1
-#endif
+// One block's share of one time step: tile (tzi, tyi) of the (y, z) plane over
+// x-chunk `chunk`, where L = (chunk * nty + tyi) * ntz + tzi.
 template <int DIM, int R, int VZ, int TZL, int TY, bool IMG>
-__global__ __launch_bounds__(TZL* TY) __attribute__((amdgpu_waves_per_eu(WAVE_MIN_WAVES, 8)))
-void k_step_stream(StepArgs a)
+__device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
 {
     using T = Tile<DIM, R, VZ, TZL, TY>;
     constexpr int NT = T::NT, TZ = T::TZ, RZ = T::RZ, PITCH = T::PITCH, S = T::S, KH = T::KH;
@@ -204,15 +202,7 @@ void k_step_stream(StepArgs a)
 
     const int64_t nx = a.nx, ny = a.ny, nz = a.nz;
     const int64_t sy = nz, sx = ny * nz;
-    const int64_t b = blockIdx.x;
     const int tid = threadIdx.x;
-    if (b >= a.stencil_blocks) {
-        const int64_t p = (b - a.stencil_blocks) * NT + tid;
-        if (p < a.smp.npts) a.smp_out[p] = sample_point<DIM>(a.smp, a.cur, p, sy, sx);
-        return;
-    }
-    int64_t L = b;
-    if (a.remap) L = (b & 7) * (a.stencil_blocks >> 3) + (b >> 3);
     const int tzi = (int)(L % a.ntz);
     const int64_t t1 = L / a.ntz;
     const int tyi = (int)(t1 % a.nty);
@@ -398,6 +388,119 @@ void k_step_stream(StepArgs a)
     }
 }
 
+// Single shot: blocks [0, stencil_blocks) are tiles, the rest sample receivers.
+template <int DIM, int R, int VZ, int TZL, int TY, bool IMG>
+__global__ __launch_bounds__(TZL* TY) void k_step_stream(StepArgs a)
+{
+    const int64_t b = blockIdx.x;
+    if (b >= a.stencil_blocks) {
+        const int64_t p = (b - a.stencil_blocks) * (TZL * TY) + threadIdx.x;
+        if (p < a.smp.npts) a.smp_out[p] = sample_point<DIM>(a.smp, a.cur, p, a.nz, a.ny * a.nz);
+        return;
+    }
+    int64_t L = b;
+    if (a.remap) L = (b & 7) * (a.stencil_blocks >> 3) + (b >> 3);
+    stream_tile<DIM, R, VZ, TZL, TY, IMG>(a, L);
+}
+
+// Many shots in one launch: block b belongs to the shot s with
+// begin[s] <= b < begin[s+1]; within a shot the layout is that of the single
+// shot kernel (tiles, then receiver samplers).  Step n of every shot: the
+// wavefield pair alternates roles, q and d rows are those of step n.
+template <int DIM, int R, int VZ, int TZL, int TY>
+__global__ __launch_bounds__(TZL* TY) void k_step_batch(const ShotDesc* __restrict__ shots,
+                                                        const int64_t* __restrict__ begin,
+                                                        int32_t nshots, int32_t n)
+{
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = nshots - 1;
+    while (lo < hi) {                       // last shot with begin[s] <= b
+        const int mid = (lo + hi + 1) >> 1;
+        if (begin[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const ShotDesc& D = shots[lo];
+    StepArgs a = D.a;
+    float* even = D.buf[0];
+    float* odd = D.buf[1];
+    a.cur = (n & 1) ? odd : even;
+    a.other = (n & 1) ? even : odd;
+    a.out = (n & 1) ? even : odd;
+    a.inj_val = D.nsrc ? D.q + (int64_t)n * D.nsrc : nullptr;
+    a.smp_out = D.nrec ? D.d + (int64_t)n * D.nrec : nullptr;
+    const int64_t lb = b - begin[lo];
+    if (lb >= a.stencil_blocks) {
+        const int64_t p = (lb - a.stencil_blocks) * (TZL * TY) + threadIdx.x;
+        if (p < a.smp.npts && a.smp_out) a.smp_out[p] = sample_point<DIM>(a.smp, a.cur, p, a.nz, a.ny * a.nz);
+        return;
+    }
+    stream_tile<DIM, R, VZ, TZL, TY, false>(a, lb);
+}
+
+
+template <int DIM_, int R_, int VZ_, int TZL_, int TY_>
+struct Cfg {
+    static constexpr int DIM = DIM_, R = R_, VZ = VZ_, TZL = TZL_, TY = TY_;
+    using T = Tile<DIM_, R_, VZ_, TZL_, TY_>;
+};
+
+// Block shapes: 2D (scalar lanes along z): 256, 128 or 64 z-points per block;
+// 3D with nz % 4 == 0 (four z-points per lane, 16 lanes per row): 16 or 8 rows;
+// other 3D grids: 64 scalar lanes x 4 rows.
+template <int DIM, int R, class F>
+hipError_t with_shape(int variant, int64_t nz, F&& f)
+{
+    if constexpr (DIM == 2) {
+        if (variant == 1) return f(Cfg<2, R, 1, 128, 1>{});
+        if (variant == 2) return f(Cfg<2, R, 1, 64, 1>{});
+        return f(Cfg<2, R, 1, 256, 1>{});
+    } else {
+        if (nz % 4 == 0) {
+            if (variant == 1) return f(Cfg<3, R, 4, 16, 8>{});
+            return f(Cfg<3, R, 4, 16, 16>{});
+        }
+        return f(Cfg<3, R, 1, 64, 4>{});
+    }
+}
+
+template <class F>
+hipError_t with_cfg(int ndim, int order, int variant, int64_t nz, F&& f)
+{
+#define WAVE_CASE(O) \
+    case O: return ndim == 2 ? with_shape<2, O / 2>(variant, nz, f) : with_shape<3, O / 2>(variant, nz, f);
+    switch (order) {
+        WAVE_CASE(2) WAVE_CASE(4) WAVE_CASE(6) WAVE_CASE(8)
+        WAVE_CASE(10) WAVE_CASE(12) WAVE_CASE(14) WAVE_CASE(16)
+    default: return hipErrorInvalidValue;
+    }
+#undef WAVE_CASE
+}
+
+template <class C>
+int64_t plan_t(StepArgs& a, int xchunk)
+{
+    using T = typename C::T;
+    a.ntz = (int32_t)((a.nz + T::TZ - 1) / T::TZ);
+    a.nty = C::DIM == 3 ? (int32_t)((a.ny + C::TY - 1) / C::TY) : 1;
+    const int64_t tiles = (int64_t)a.ntz * a.nty;
+    if (xchunk <= 0) {
+        // about eight blocks per CU on 256 CUs (two residency rounds), so that
+        // enough loads are in flight, but no chunk shorter than 2R planes
+        const int64_t want_chunks = (2048 + tiles - 1) / tiles;
+        int64_t xc = (a.nx + want_chunks - 1) / want_chunks;
+        if (xc < 2 * C::R) xc = 2 * C::R;
+        xchunk = (int)(xc < a.nx ? xc : a.nx);
+    }
+    if (xchunk > a.nx) xchunk = (int)a.nx;
+    a.xchunk = xchunk;
+    const int64_t nchunk = (a.nx + xchunk - 1) / xchunk;
+    a.stencil_blocks = tiles * nchunk;
+    a.remap = (a.stencil_blocks % 8 == 0) ? 1 : 0;
+    int64_t nsb = 0;
+    if (a.smp_out && a.smp.npts > 0) nsb = (a.smp.npts + T::NT - 1) / T::NT;
+    return a.stencil_blocks + nsb;
+}
+
 template <int DIM, int R>
 hipError_t launch_naive_t(const StepArgs& a0, hipStream_t s)
 {
@@ -415,70 +518,22 @@ hipError_t launch_naive_t(const StepArgs& a0, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int DIM, int R, int VZ, int TZL, int TY>
-hipError_t launch_stream_t(const StepArgs& a0, hipStream_t s, int xchunk)
-{
-    using T = Tile<DIM, R, VZ, TZL, TY>;
-    StepArgs a = a0;
-    a.ntz = (int32_t)((a.nz + T::TZ - 1) / T::TZ);
-    a.nty = DIM == 3 ? (int32_t)((a.ny + TY - 1) / TY) : 1;
-    const int64_t tiles = (int64_t)a.ntz * a.nty;
-    if (xchunk <= 0) {
-        // about eight blocks per CU on 256 CUs (two residency rounds), so that
-        // enough loads are in flight, but no chunk shorter than 2R planes
-        const int64_t want_chunks = (2048 + tiles - 1) / tiles;
-        int64_t xc = (a.nx + want_chunks - 1) / want_chunks;
-        if (xc < 2 * R) xc = 2 * R;
-        xchunk = (int)(xc < a.nx ? xc : a.nx);
-    }
-    a.xchunk = xchunk;
-    const int64_t nchunk = (a.nx + xchunk - 1) / xchunk;
-    a.stencil_blocks = tiles * nchunk;
-    a.remap = (a.stencil_blocks % 8 == 0) ? 1 : 0;
-    int64_t nsb = 0;
-    if (a.smp_out && a.smp.npts > 0) nsb = (a.smp.npts + T::NT - 1) / T::NT;
-    else a.smp.npts = 0;
-    const int64_t blocks = a.stencil_blocks + nsb;
-    if (a.img_grad)
-        hipLaunchKernelGGL((k_step_stream<DIM, R, VZ, TZL, TY, true>), dim3((unsigned)blocks),
-                           dim3(T::NT), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_step_stream<DIM, R, VZ, TZL, TY, false>), dim3((unsigned)blocks),
-                           dim3(T::NT), 0, s, a);
-    return hipGetLastError();
-}
-
-template <int DIM, int R>
-hipError_t launch_r(const StepArgs& a, hipStream_t s, int kernel, int xchunk)
-{
-    if (kernel == kNaive) return launch_naive_t<DIM, R>(a, s);
-    if (DIM == 2) return launch_stream_t<2, R, 1, 256, 1>(a, s, xchunk);
-#ifndef WAVE_TILE_Y3
-#define WAVE_TILE_Y3 16
-#endif
-    if (a.nz % 4 == 0) return launch_stream_t<3, R, 4, 16, WAVE_TILE_Y3>(a, s, xchunk);
-    return launch_stream_t<3, R, 1, 64, 4>(a, s, xchunk);
-}
-
 template <int DIM>
-hipError_t launch_dim(int order, const StepArgs& a, hipStream_t s, int kernel, int xchunk)
+hipError_t launch_naive_dim(int order, const StepArgs& a, hipStream_t s)
 {
     switch (order) {
-    case 2: return launch_r<DIM, 1>(a, s, kernel, xchunk);
-    case 4: return launch_r<DIM, 2>(a, s, kernel, xchunk);
-    case 6: return launch_r<DIM, 3>(a, s, kernel, xchunk);
-    case 8: return launch_r<DIM, 4>(a, s, kernel, xchunk);
-    case 10: return launch_r<DIM, 5>(a, s, kernel, xchunk);
-    case 12: return launch_r<DIM, 6>(a, s, kernel, xchunk);
-    case 14: return launch_r<DIM, 7>(a, s, kernel, xchunk);
-    case 16: return launch_r<DIM, 8>(a, s, kernel, xchunk);
+    case 2: return launch_naive_t<DIM, 1>(a, s);
+    case 4: return launch_naive_t<DIM, 2>(a, s);
+    case 6: return launch_naive_t<DIM, 3>(a, s);
+    case 8: return launch_naive_t<DIM, 4>(a, s);
+    case 10: return launch_naive_t<DIM, 5>(a, s);
+    case 12: return launch_naive_t<DIM, 6>(a, s);
+    case 14: return launch_naive_t<DIM, 7>(a, s);
+    case 16: return launch_naive_t<DIM, 8>(a, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-// One pass over m and eta: validity counts and min(m) per block for the
-// host-side checks, and the step coefficients
-//   alpha = dt^2 / (m + eta dt/2),  beta = (m - eta dt/2) / (m + eta dt/2).
 __global__ __launch_bounds__(kBlock) void k_check_fields(const float* __restrict__ m,
                                                          const float* __restrict__ eta,
                                                          int64_t n, float* __restrict__ partial,
@@ -681,12 +736,51 @@ int grid_for(int64_t n)
 
 }  // namespace
 
-hipError_t launch_step(int ndim, int order, const StepArgs& a, hipStream_t s, int kernel,
-                       int xchunk)
+int tile_variants(int ndim, int64_t nz)
 {
-    if (ndim == 2) return launch_dim<2>(order, a, s, kernel, xchunk);
-    if (ndim == 3) return launch_dim<3>(order, a, s, kernel, xchunk);
-    return hipErrorInvalidValue;
+    if (ndim == 2) return 3;
+    return nz % 4 == 0 ? 2 : 1;
+}
+
+int64_t plan_tiles(int ndim, int order, TileCfg cfg, StepArgs& a)
+{
+    int64_t blocks = -1;
+    (void)with_cfg(ndim, order, cfg.variant, a.nz, [&](auto C) {
+        blocks = plan_t<decltype(C)>(a, cfg.xchunk);
+        return hipSuccess;
+    });
+    return blocks;
+}
+
+hipError_t launch_step(int ndim, int order, const StepArgs& a0, hipStream_t s, int kernel,
+                       TileCfg cfg)
+{
+    if (kernel == kNaive) return ndim == 2 ? launch_naive_dim<2>(order, a0, s) : launch_naive_dim<3>(order, a0, s);
+    return with_cfg(ndim, order, cfg.variant, a0.nz, [&](auto C) {
+        using CC = decltype(C);
+        StepArgs a = a0;
+        const int64_t blocks = plan_t<CC>(a, cfg.xchunk);
+        if (!(a.smp_out && a.smp.npts > 0)) a.smp.npts = 0;
+        if (a.img_grad)
+            hipLaunchKernelGGL((k_step_stream<CC::DIM, CC::R, CC::VZ, CC::TZL, CC::TY, true>),
+                               dim3((unsigned)blocks), dim3(CC::T::NT), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_step_stream<CC::DIM, CC::R, CC::VZ, CC::TZL, CC::TY, false>),
+                               dim3((unsigned)blocks), dim3(CC::T::NT), 0, s, a);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_batch(int ndim, int order, int64_t nz_any, TileCfg cfg, const ShotDesc* shots,
+                        const int64_t* begin, int32_t nshots, int64_t blocks, int32_t n,
+                        hipStream_t s)
+{
+    return with_cfg(ndim, order, cfg.variant, nz_any, [&](auto C) {
+        using CC = decltype(C);
+        hipLaunchKernelGGL((k_step_batch<CC::DIM, CC::R, CC::VZ, CC::TZL, CC::TY>),
+                           dim3((unsigned)blocks), dim3(CC::T::NT), 0, s, shots, begin, nshots, n);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_check_fields(const float* m, const float* eta, int64_t n, float* partial,

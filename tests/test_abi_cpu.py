@@ -118,3 +118,17 @@ def test_python_api_imports_without_gpu():
     assert pkg.Geometry is api.Geometry and callable(pkg.wave_apply)
     g = api.Geometry((10, 12), (5.0, 5.0), 4, 1e-3, 7)
     assert g.grid().nt == 7
+
+
+def test_batch_rejects_mismatched_shots_before_device_work():
+    g1 = L.make_grid((20, 30), (10.0, 10.0), 8, 1e-3, 10)
+    g2 = L.make_grid((25, 30), (10.0, 10.0), 8, 1e-3, 11)
+    arr = (L.Shot * 2)()
+    for s, g in zip(arr, (g1, g2)):
+        s.grid = g
+        s.m = 1 << 20
+    n = C.c_size_t(0)
+    assert L.lib().wave_batch_workspace_size(2, arr, None, C.byref(n)) == L.WAVE_EINVAL
+    assert b"same ndim" in L.lib().wave_last_error()
+    arr[1].grid = L.make_grid((25, 30), (10.0, 10.0), 8, 1e-3, 10)
+    assert L.lib().wave_batch_workspace_size(2, arr, None, C.byref(n)) == 0 and n.value > 0

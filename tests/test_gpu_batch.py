@@ -1,0 +1,114 @@
+"""Batched shots and tiles: every shot of a batch (one launch per step over
+all shots, captured in a hipGraph) must equal the same shot run alone, bit
+for bit; explicit and tuned tiles must not change any result; a couple of
+shots are also checked against the oracle."""
+import numpy as np
+import pytest
+
+from gpu_util import device_inputs, oracle_forward, rel_l2
+from paper_1609_03361_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+def _shots(dev, n=5, nt=120):
+    import torch
+    from paper_1609_03361_amd import api
+    probs = synth.config_batched_2d(nshots=n, nx=301, nz=81, nt=nt, wmin=60, nrec=37)
+    out = []
+    for p in probs:
+        geom, m, eta, q = device_inputs(p, dev)
+        out.append((geom, m, eta, q))
+    return probs, out
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_equals_single_shots_bitwise(dev, graph):
+    import torch
+    from paper_1609_03361_amd import api
+    probs, shots = _shots(dev)
+    print("widths", [p.shape[0] for p in probs], flush=True)
+    d, u = api.forward_batch(shots, return_final=True, graph=graph)
+    for i, (geom, m, eta, q) in enumerate(shots):
+        ds, us = api.forward(geom, m, eta, q, return_final=True)
+        torch.cuda.synchronize()
+        assert torch.equal(ds, d[i]), i
+        assert torch.equal(us, u[i]), i
+
+
+def test_batch_graph_replay_is_reused_and_stable(dev):
+    import torch
+    from paper_1609_03361_amd import api
+    probs, shots = _shots(dev, n=3, nt=60)
+    a = api.forward_batch(shots, return_final=True)
+    b = api.forward_batch(shots, return_final=True)
+    torch.cuda.synchronize()
+    for x, y in zip(a[0] + a[1], b[0] + b[1]):
+        assert torch.equal(x, y)
+
+
+def test_batch_shots_match_oracle(dev):
+    import torch
+    from paper_1609_03361_amd import api
+    probs, shots = _shots(dev, n=3, nt=150)
+    d, u = api.forward_batch(shots, return_final=True)
+    torch.cuda.synchronize()
+    for i in (0, 2):
+        ref = oracle_forward(probs[i])
+        assert rel_l2(d[i].cpu().numpy(), ref["d"]) < 1e-5
+        assert rel_l2(u[i].cpu().numpy(), ref["u"]) < 1e-5
+
+
+def test_3d_batch_equals_single(dev):
+    import torch
+    from paper_1609_03361_amd import api
+    shots = []
+    for k, shape in enumerate([(20, 18, 24), (31, 22, 24), (17, 26, 24)]):
+        p = synth.random_problem(shape, 8, 30, seed=40 + k, nsrc=2, nrec=6)
+        p.dt = 0.0004
+        shots.append(device_inputs(p, dev))
+    d, u = api.forward_batch(shots, return_final=True)
+    for i, (geom, m, eta, q) in enumerate(shots):
+        ds, us = api.forward(geom, m, eta, q, return_final=True)
+        torch.cuda.synchronize()
+        assert torch.equal(ds, d[i]) and torch.equal(us, u[i])
+
+
+@pytest.mark.parametrize("shape,order", [((33, 29, 40), 8), ((60, 70), 8), ((25, 23, 31), 4)])
+def test_tiles_do_not_change_results(dev, shape, order):
+    import torch
+    from paper_1609_03361_amd import api
+    p = synth.random_problem(shape, order, 16, seed=5, nsrc=3, nrec=8)
+    geom, m, eta, q = device_inputs(p, dev)
+    ref = api.forward(geom, m, eta, q, return_final=True)
+    nvar = 3 if len(shape) == 2 else (2 if shape[2] % 4 == 0 else 1)
+    for v in range(nvar):
+        for x in (1, order // 2, 7, 64):
+            got = api.forward(geom, m, eta, q, return_final=True, tile=api.tile_id(v, x))
+            torch.cuda.synchronize()
+            assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), (v, x)
+
+
+def test_tuner_picks_a_tile_and_results_stay_bitwise(dev):
+    import torch
+    from paper_1609_03361_amd import api
+    p = synth.random_problem((48, 44, 64), 8, 12, seed=6, nsrc=2, nrec=5)
+    geom, m, eta, q = device_inputs(p, dev)
+    ref = api.forward(geom, m, eta, q, return_final=True)
+    tile, us = api.tune(geom, steps=5)
+    print(f"tuned tile variant {tile >> 16} x-chunk {tile & 0xffff}: {us:.2f} us/step", flush=True)
+    assert tile > 0 and us > 0
+    got = api.forward(geom, m, eta, q, return_final=True)      # tile 0 -> cached tile
+    torch.cuda.synchronize()
+    assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])
+    probs, shots = _shots(dev, n=3, nt=20)
+    bt, bus = api.tune_batch(shots, steps=3)
+    print(f"batch tile variant {bt >> 16} x-chunk {bt & 0xffff}: {bus:.2f} us/step", flush=True)
+    assert bt > 0

@@ -84,7 +84,7 @@ struct TileCfg {
 inline TileCfg tile_from_id(int id) { TileCfg c; c.variant = (id >> 16) & 0xff; c.xchunk = id & 0xffff; return c; }
 inline int tile_id(const TileCfg& c) { return (c.variant << 16) | c.xchunk; }
 
-// Number of block-shape variants for a grid (2D: 3; 3D with nz % 4 == 0: 2; else 1).
+// Number of block-shape variants for a grid (2D: 3; 3D with nz % 4 == 0: 3; else 1).
 int tile_variants(int ndim, int64_t nz);
 // Fill the tiling fields of `a` (ntz, nty, xchunk, stencil_blocks, remap) for
 // `cfg`; returns the block count of one launch including receiver samplers.

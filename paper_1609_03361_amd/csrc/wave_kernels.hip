@@ -145,30 +145,22 @@ __device__ __forceinline__ void vstore(float* p, const Vec<VZ>& v)
     *reinterpret_cast<Vec<VZ>*>(p) = v;
 }
 
-// Operands touched once per step (previous level, coefficients, output) are
-// streamed with the non-temporal hint so they do not evict the wavefield
-// planes that neighbouring tiles re-read as halos.
-#ifndef WAVE_STREAM_HINT
-#define WAVE_STREAM_HINT 1
-#endif
-template <int VZ>
+// Operands touched once per step (previous level, coefficients, output).
+// With NT they carry the non-temporal hint, which keeps them from evicting
+// wavefield planes that later tiles re-read; measured on gfx950 it pays only
+// where the halos are not loaded early (see Tile::LEAD).
+template <int VZ, bool NT>
 __device__ __forceinline__ Vec<VZ> vload_once(const float* p)
 {
-#if WAVE_STREAM_HINT
-    return __builtin_nontemporal_load(reinterpret_cast<const Vec<VZ>*>(p));
-#else
-    return *reinterpret_cast<const Vec<VZ>*>(p);
-#endif
+    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const Vec<VZ>*>(p));
+    else return *reinterpret_cast<const Vec<VZ>*>(p);
 }
 
-template <int VZ>
+template <int VZ, bool NT>
 __device__ __forceinline__ void vstore_once(float* p, const Vec<VZ>& v)
 {
-#if WAVE_STREAM_HINT
-    __builtin_nontemporal_store(v, reinterpret_cast<Vec<VZ>*>(p));
-#else
-    *reinterpret_cast<Vec<VZ>*>(p) = v;
-#endif
+    if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<Vec<VZ>*>(p));
+    else *reinterpret_cast<Vec<VZ>*>(p) = v;
 }
 
 // Wait for this wave's LDS traffic, then meet the block at the barrier.
@@ -189,6 +181,12 @@ struct Tile {
     static constexpr int NHZ = TY * 2 * (RZ / VZ);          // z-halo vectors per plane
     static constexpr int KH = (NHY + NHZ + NT - 1) / NT;    // halo vectors per thread
     static constexpr int S = 2 * R + 2;                     // queue slots
+    // Halo lead: in 3D, the y/z halo of plane p is loaded together with the
+    // queue load of p (R+1 planes before its use) and held in registers, so it
+    // is read while the neighbouring tile's load of the same rows is still in
+    // L2.  Above R = 6 the extra registers would cost occupancy.
+    static constexpr bool LEAD = DIM == 3 && R <= 6;
+    static constexpr bool HINT = !LEAD;
 };
 
 // One block's share of one time step: tile (tzi, tyi) of the (y, z) plane over
@@ -258,20 +256,34 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
         Vec<VZ> uo, al, be;
     };
     Pre pre0, pre1;
+    // halo ring of the lead mode (one slot per plane of lead)
+    constexpr int HS = T::LEAD ? R + 1 : 1;
+    Vec<VZ> hring[HS][KH];
+    auto load_halo = [&](Vec<VZ>* dst, int64_t xx) {
+#pragma unroll
+        for (int k = 0; k < KH; ++k) {
+            dst[k] = vzero<VZ>();
+            if (hoff[k] >= 0 && xx < nx) dst[k] = vload<VZ>(u + xx * sx + hoff[k]);
+        }
+    };
     auto fetch = [&](Pre& P, int64_t xx) {
 #pragma unroll
         for (int k = 0; k < KH; ++k) {
             P.halo[k] = vzero<VZ>();
-            if (hoff[k] >= 0) P.halo[k] = vload<VZ>(u + xx * sx + hoff[k]);
+            if (!T::LEAD && hoff[k] >= 0) P.halo[k] = vload<VZ>(u + xx * sx + hoff[k]);
         }
         P.uo = P.al = P.be = vzero<VZ>();
         if (own) {
-            P.uo = vload_once<VZ>(a.other + xx * sx + col);
-            P.al = vload_once<VZ>(a.alpha + xx * sx + col);
-            P.be = vload_once<VZ>(a.beta + xx * sx + col);
+            P.uo = vload_once<VZ, T::HINT>(a.other + xx * sx + col);
+            P.al = vload_once<VZ, T::HINT>(a.alpha + xx * sx + col);
+            P.be = vload_once<VZ, T::HINT>(a.beta + xx * sx + col);
         }
     };
     if (xa < xb) fetch(pre0, xa);
+    if (T::LEAD) {
+#pragma unroll
+        for (int k = 0; k < HS; ++k) load_halo(hring[k], xa + k);
+    }
 
     const int row_c = (ty + (DIM == 3 ? R : 0)) * PITCH + RZ + tz * VZ;
 
@@ -285,9 +297,17 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
         float* Ls = lds[B];
         const Vec<VZ> c = Q[(U + R) % S];
         vstore<VZ>(Ls + row_c, c);
+        if (T::LEAD) {
+            Vec<VZ>* hr = hring[U % HS];
 #pragma unroll
-        for (int k = 0; k < KH; ++k)
-            if (hlds[k] >= 0) vstore<VZ>(Ls + hlds[k], P.halo[k]);
+            for (int k = 0; k < KH; ++k)
+                if (hlds[k] >= 0) vstore<VZ>(Ls + hlds[k], hr[k]);
+            if (x + R + 1 < xb) load_halo(hr, x + R + 1);
+        } else {
+#pragma unroll
+            for (int k = 0; k < KH; ++k)
+                if (hlds[k] >= 0) vstore<VZ>(Ls + hlds[k], P.halo[k]);
+        }
         lds_barrier();
 
         float lap[VZ], m2c[VZ];
@@ -376,7 +396,7 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
                 }
                 vstore<VZ>(a.img_grad + off, g);
             }
-            vstore_once<VZ>(a.out + off, o);
+            vstore_once<VZ, T::HINT>(a.out + off, o);
         }
     };
 
@@ -445,8 +465,8 @@ struct Cfg {
 };
 
 // Block shapes: 2D (scalar lanes along z): 256, 128 or 64 z-points per block;
-// 3D with nz % 4 == 0 (four z-points per lane, 16 lanes per row): 16 or 8 rows;
-// other 3D grids: 64 scalar lanes x 4 rows.
+// 3D with nz % 4 == 0 (four z-points per lane): 64 z x 16 rows, 64 z x 8 rows
+// or 32 z x 32 rows; other 3D grids: 64 scalar lanes x 4 rows.
 template <int DIM, int R, class F>
 hipError_t with_shape(int variant, int64_t nz, F&& f)
 {
@@ -457,6 +477,7 @@ hipError_t with_shape(int variant, int64_t nz, F&& f)
     } else {
         if (nz % 4 == 0) {
             if (variant == 1) return f(Cfg<3, R, 4, 16, 8>{});
+            if (variant == 2) return f(Cfg<3, R, 4, 8, 32>{});
             return f(Cfg<3, R, 4, 16, 16>{});
         }
         return f(Cfg<3, R, 1, 64, 4>{});
@@ -484,11 +505,13 @@ int64_t plan_t(StepArgs& a, int xchunk)
     a.nty = C::DIM == 3 ? (int32_t)((a.ny + C::TY - 1) / C::TY) : 1;
     const int64_t tiles = (int64_t)a.ntz * a.nty;
     if (xchunk <= 0) {
-        // about eight blocks per CU on 256 CUs (two residency rounds), so that
-        // enough loads are in flight, but no chunk shorter than 2R planes
+        // about eight blocks per CU on 256 CUs, so that enough loads are in
+        // flight, but no chunk shorter than 2R planes (3D: 16), which would
+        // spend most of the block on its 2R-plane prologue
         const int64_t want_chunks = (2048 + tiles - 1) / tiles;
         int64_t xc = (a.nx + want_chunks - 1) / want_chunks;
-        if (xc < 2 * C::R) xc = 2 * C::R;
+        const int64_t xmin = C::DIM == 3 ? (2 * C::R > 16 ? 2 * C::R : 16) : 2 * C::R;
+        if (xc < xmin) xc = xmin;
         xchunk = (int)(xc < a.nx ? xc : a.nx);
     }
     if (xchunk > a.nx) xchunk = (int)a.nx;
@@ -739,7 +762,7 @@ int grid_for(int64_t n)
 int tile_variants(int ndim, int64_t nz)
 {
     if (ndim == 2) return 3;
-    return nz % 4 == 0 ? 2 : 1;
+    return nz % 4 == 0 ? 3 : 1;
 }
 
 int64_t plan_tiles(int ndim, int order, TileCfg cfg, StepArgs& a)

@@ -88,7 +88,7 @@ def test_tiles_do_not_change_results(dev, shape, order):
     p = synth.random_problem(shape, order, 16, seed=5, nsrc=3, nrec=8)
     geom, m, eta, q = device_inputs(p, dev)
     ref = api.forward(geom, m, eta, q, return_final=True)
-    nvar = 3 if len(shape) == 2 else (2 if shape[2] % 4 == 0 else 1)
+    nvar = 3 if len(shape) == 2 else (3 if shape[2] % 4 == 0 else 1)
     for v in range(nvar):
         for x in (1, order // 2, 7, 64):
             got = api.forward(geom, m, eta, q, return_final=True, tile=api.tile_id(v, x))

@@ -37,6 +37,20 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def measured_traffic(workload):
+    """HBM bytes per step launch from the committed rocprofv3 --pmc summary
+    (FETCH_SIZE and WRITE_SIZE scaled by the plain-copy calibration), or None
+    when the step kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
+    src = os.path.join(ROOT, "paper_1609_03361_amd", "csrc", "wave_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    return rec["hbm_bytes_per_launch"] if rec.get("kernel_source_sha256_16") == sha else None
+
+
 def cpu_baseline(p, steps):
     """The FP64 oracle on the host cores, on the first `steps` time steps of
     the same workload (full grid)."""
@@ -235,7 +249,8 @@ def main():
                    "bench_step": "one full forward modelling run"},
         "hbm_roofline_frac": round(value * BYTES_PER_UPDATE / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(p.name) if args.tile == 0 else None,
                      "kernel": "leapfrog step", "launch_ms": round(per_launch_ms, 5),
                      "alg_bytes_per_launch": alg_bytes},
     }

@@ -144,6 +144,7 @@ def batched_bench(dev, reps=2):
         return best
 
     tb = timed(lambda: api.forward_batch(shots, tile=tile))
+    tp = timed(lambda: api.forward_batch(shots, tile=tile, persistent=True), reps=1)
     # the same model as one shot, through the single-shot path
     m_full, _ = synth.layered((2001, 801), 4)
     vmax = float(np.max(1.0 / np.sqrt(m_full.astype(np.float64))))
@@ -159,6 +160,8 @@ def batched_bench(dev, reps=2):
     return {"workload": f"{len(probs)} 2D shots, widths {min(p.shape[0] for p in probs)}-"
                         f"{max(p.shape[0] for p in probs)} x 801, order 8, {p0.nt} steps",
             "batched_gpts": round(batched, 2), "batched_s": round(tb, 4),
+            "mode": "per-step launches over all shots, replayed from a hipGraph",
+            "persistent_single_launch_s": round(tp, 4),
             "tile": {"variant": tile >> 16, "xchunk": tile & 0xffff, "tuned_us_per_step": round(tune_us, 2)},
             "single_shot_full_model_gpts": round(single, 2),
             "batched_vs_single": round(batched / single, 3)}

@@ -90,7 +90,8 @@ typedef struct {
     int32_t flags;            /* WAVE_FLAG_* bits */
 } wave_opts;
 
-#define WAVE_FLAG_NO_GRAPH 1  /* batch: launch the steps one by one instead of replaying a hipGraph */
+#define WAVE_FLAG_NO_GRAPH 1    /* batch: launch the steps one by one instead of replaying a hipGraph */
+#define WAVE_FLAG_PERSISTENT 2  /* batch: one persistent co-resident launch for all steps (see below) */
 
 typedef enum {
     WAVE_OP_FORWARD = 0,      /* wave_forward (no checkpoints) */
@@ -201,7 +202,16 @@ typedef struct {
 
 int wave_batch_workspace_size(int32_t nshots, const wave_shot* shots, const wave_opts* opts,
                               size_t* bytes);
+/* With opts->flags & WAVE_FLAG_PERSISTENT the whole time loop of all shots is
+ * one cooperative launch (the runtime guarantees that all its blocks are
+ * resident at once), with a device-wide barrier between steps.  That mode
+ * waits for the launch before returning and reports WAVE_EHIP if a barrier
+ * wait ever exceeded its bound. */
 int wave_forward_batch(int32_t nshots, const wave_shot* shots, const wave_opts* opts, void* stream);
+/* How this thread's last wave_forward_batch ran: 0 per-step launches replayed
+ * from a hipGraph, 1 per-step launches, 2 one persistent launch, 3 one
+ * persistent launch replayed from a hipGraph; -1 if none yet. */
+int wave_last_batch_mode(void);
 
 /*
  * Tile autotuner (the paper's brute-force search over loop-blocking sizes,

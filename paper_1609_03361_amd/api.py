@@ -216,15 +216,22 @@ class _Batch:
         return buf, L.make_opts(buf.data_ptr() + off, int(nbytes.value), **kw)
 
 
-def forward_batch(shots, return_final=False, tile=0, graph=True):
-    """Forward-model many shots in one launch per step (captured in a hipGraph).
-    ``shots``: list of (Geometry, m, eta, q).  Returns the list of traces (and
-    of final wavefields if ``return_final``)."""
+def forward_batch(shots, return_final=False, tile=0, graph=True, persistent=False):
+    """Forward-model many shots: one launch per step over all shots, replayed
+    from a hipGraph (``graph``), or one persistent launch for all steps
+    (``persistent``).  ``shots``: list of (Geometry, m, eta, q).  Returns the
+    list of traces (and of final wavefields if ``return_final``)."""
     B = _Batch(shots, return_final)
-    ws, o = B.workspace(tile=tile, flags=0 if graph else L.WAVE_FLAG_NO_GRAPH)
+    flags = (0 if graph else L.WAVE_FLAG_NO_GRAPH) | (L.WAVE_FLAG_PERSISTENT if persistent else 0)
+    ws, o = B.workspace(tile=tile, flags=flags)
     L.check(L.lib().wave_forward_batch(B.n, B.arr, C.byref(o), _stream(B.dev)),
             "wave_forward_batch")
     return (B.d, B.uf) if return_final else B.d
+
+
+def last_batch_mode() -> int:
+    """0: per-step graph, 1: per-step launches, 2: persistent, 3: persistent in a graph."""
+    return int(L.lib().wave_last_batch_mode())
 
 
 def tune_batch(shots, steps: int = 10):

@@ -394,7 +394,6 @@ struct Ctx {
     float cx[kMaxHalf + 1] = {}, cy[kMaxHalf + 1] = {}, cz[kMaxHalf + 1] = {};
     HostPoints rec, src;
     HostInject inj_src, inj_rec;
-    int kernel = kStream;   // step kernel variant
     TileCfg cfg;            // block shape and x-chunk of the streaming kernel
     template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
@@ -467,7 +466,6 @@ int setup(Ctx& C, int op, const wave_grid* grid, const float* m, const float* et
     C.ws = static_cast<char*>(o->workspace);
     C.s = static_cast<hipStream_t>(stream);
     C.cfg = o->tile > 0 ? tile_from_id(o->tile) : cached_tile(tune_key(C.G));
-    if (const char* k = std::getenv("WAVE_STEP_KERNEL")) C.kernel = std::strcmp(k, "naive") ? kStream : kNaive;
     set_weights(C);
     const bool fwd = op != WAVE_OP_ADJOINT, adj = op != WAVE_OP_FORWARD;
     if (fwd) make_inject(C.G, C.src, &C.inj_src);
@@ -553,7 +551,7 @@ void bind_sparse(const Ctx& C, StepArgs& a, int set)
 hipError_t step(const Ctx& C, const StepArgs& a)
 {
     ++g_prof.launches;
-    return launch_step(C.G.ndim, C.G.order, a, C.s, C.kernel, C.cfg);
+    return launch_step(C.G.ndim, C.G.order, a, C.s, C.cfg);
 }
 
 // Checkpoint storage: per checkpoint c two snapshot arrays (FP32: u^c and
@@ -743,7 +741,7 @@ struct BatchShot {
 
 struct BatchPlan {
     std::vector<BatchShot> shots;
-    size_t desc = 0, begin = 0, check = 0, total = 0;
+    size_t desc = 0, begin = 0, check = 0, sync = 0, total = 0;
 };
 
 constexpr int kCheckBlocksShot = 256;
@@ -756,6 +754,7 @@ int batch_plan(int32_t nshots, const wave_shot* shots, BatchPlan* B, bool build_
     B->desc = c.take(sizeof(ShotDesc) * (size_t)nshots);
     B->begin = c.take(sizeof(int64_t) * ((size_t)nshots + 1));
     B->check = c.take((size_t)nshots * kCheckBlocksShot * 3 * 4);
+    B->sync = c.take(64);
     for (int i = 0; i < nshots; ++i) {
         BatchShot& S = B->shots[i];
         int rc = make_geo(&shots[i].grid, &S.G);
@@ -938,6 +937,43 @@ struct GraphCache {
 };
 thread_local GraphCache g_graph;
 
+
+// How the last batched call ran: 0 = per-step launches replayed from a
+// hipGraph, 1 = per-step launches, 2 = one persistent launch, 3 = one
+// persistent launch captured in a hipGraph.
+thread_local int g_batch_mode = -1;
+
+// One persistent cooperative launch for all steps, then a wait and a check of
+// the barrier error word, so a barrier that did not complete is reported,
+// never left hanging.
+int run_batch_persistent(const BatchPlan& B, char* ws, TileCfg cfg, int64_t items, hipStream_t st)
+{
+    const Geo& G = B.shots[0].G;
+    const int nshots = (int)B.shots.size();
+    const ShotDesc* d_desc = reinterpret_cast<const ShotDesc*>(ws + B.desc);
+    const int64_t* d_begin = reinterpret_cast<const int64_t*>(ws + B.begin);
+    unsigned int* sync = reinterpret_cast<unsigned int*>(ws + B.sync);
+    const int32_t spin_limit = 2000000;   // a few seconds of polling per barrier at most
+    HIP_TRY(launch_fill(reinterpret_cast<float*>(sync), 2, 0.f, st));
+    int grid = 0;
+    g_prof.launches += 1;
+    // a direct cooperative launch: the runtime refuses it unless every block
+    // can be resident at once, which the device-wide barrier relies on
+    int per_cu = 4;
+    if (const char* e = std::getenv("WAVE_PERSISTENT_BLOCKS_PER_CU")) per_cu = std::max(1, std::atoi(e));
+    HIP_TRY(launch_batch_persistent(G.ndim, G.order, G.n[2], cfg, d_desc, d_begin, nshots, items,
+                                    G.nt, sync, spin_limit, per_cu, &grid, st));
+    g_batch_mode = 2;
+    unsigned int words[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(words, sync, sizeof words, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (words[1])
+        return fail(WAVE_EHIP, "persistent batch: a device-wide barrier timed out (grid %d blocks)", grid);
+    return WAVE_OK;
+}
+
+
+
 int run_batch_loop(const BatchPlan& B, char* ws, TileCfg cfg, int64_t blocks, hipStream_t st,
                    bool use_graph)
 {
@@ -945,6 +981,7 @@ int run_batch_loop(const BatchPlan& B, char* ws, TileCfg cfg, int64_t blocks, hi
     const int nshots = (int)B.shots.size();
     const ShotDesc* d_desc = reinterpret_cast<const ShotDesc*>(ws + B.desc);
     const int64_t* d_begin = reinterpret_cast<const int64_t*>(ws + B.begin);
+    g_batch_mode = use_graph ? 0 : 1;
     if (!use_graph) {
         for (int n = 0; n < G.nt; ++n) {
             ++g_prof.launches;
@@ -997,6 +1034,8 @@ extern "C" {
 const char* wave_last_error(void) { return g_error.c_str(); }
 
 const char* wave_version(void) { return "wavefd-mi355x 0.1 (gfx950)"; }
+
+int wave_last_batch_mode(void) { return g_batch_mode; }
 
 int wave_set_profiling(int32_t enable)
 {
@@ -1196,7 +1235,10 @@ int wave_forward_batch(int32_t nshots, const wave_shot* shots, const wave_opts* 
         build_descs(B, shots, ws, cfg, &desc, &begin, &blocks);
         if ((rc = upload_descs(desc, begin, ws, B, st))) return rc;
         if (prof_begin(st)) return fail(WAVE_EHIP, "profiling event failed");
-        rc = run_batch_loop(B, ws, cfg, blocks, st, !(opts->flags & WAVE_FLAG_NO_GRAPH));
+        if (opts->flags & WAVE_FLAG_PERSISTENT)
+            rc = run_batch_persistent(B, ws, cfg, blocks, st);
+        else
+            rc = run_batch_loop(B, ws, cfg, blocks, st, !(opts->flags & WAVE_FLAG_NO_GRAPH));
         if (rc) return rc;
         if (prof_end(st)) return fail(WAVE_EHIP, "profiling event failed");
         const int last = B.shots[0].G.nt & 1;
@@ -1239,11 +1281,11 @@ int wave_tune(const wave_grid* grid, const wave_opts* opts, int32_t steps, void*
         double best = 1e300;
         TileCfg best_cfg;
         for (const TileCfg& cfg : tile_candidates(C.G.ndim, C.G.half, C.G.n[0], C.G.n[2])) {
-            for (int w = 0; w < 2; ++w) HIP_TRY(launch_step(C.G.ndim, C.G.order, a, C.s, kStream, cfg));
+            for (int w = 0; w < 2; ++w) HIP_TRY(launch_step(C.G.ndim, C.G.order, a, C.s, cfg));
             double t = 1e300;
             for (int rep = 0; rep < 3; ++rep) {
                 HIP_TRY(hipEventRecord(ev.a, C.s));
-                for (int i = 0; i < steps; ++i) HIP_TRY(launch_step(C.G.ndim, C.G.order, a, C.s, kStream, cfg));
+                for (int i = 0; i < steps; ++i) HIP_TRY(launch_step(C.G.ndim, C.G.order, a, C.s, cfg));
                 HIP_TRY(hipEventRecord(ev.b, C.s));
                 HIP_TRY(hipEventSynchronize(ev.b));
                 float ms = 0.f;

@@ -71,10 +71,6 @@ struct ShotDesc {
     int32_t nsrc, nrec;
 };
 
-// Kernel variants of the time step.  kStream: 2.5D register-streaming along
-// x with (y, z) planes staged in LDS; kNaive: one thread per point.
-enum StepKernel { kStream = 0, kNaive = 1 };
-
 // Tile configuration of the streaming kernel: block shape variant and x-chunk
 // length (0 = chosen from the grid).  Public tile id: (variant << 16) | xchunk.
 struct TileCfg {
@@ -90,15 +86,22 @@ int tile_variants(int ndim, int64_t nz);
 // `cfg`; returns the block count of one launch including receiver samplers.
 int64_t plan_tiles(int ndim, int order, TileCfg cfg, StepArgs& a);
 
-// Launchers (return hipError_t of the launch).  `a` must have been planned
-// with the same cfg unless kernel == kNaive.
-hipError_t launch_step(int ndim, int order, const StepArgs& a, hipStream_t s, int kernel,
-                       TileCfg cfg);
+// Launch one time step of the 2.5D streaming kernel (plans `a` for cfg).
+hipError_t launch_step(int ndim, int order, const StepArgs& a, hipStream_t s, TileCfg cfg);
 // One step of every shot in one launch; every shot must be planned with the
 // same cfg; `begin` holds the first block of each shot and the total.
 hipError_t launch_batch(int ndim, int order, int64_t nz_any, TileCfg cfg, const ShotDesc* shots,
                         const int64_t* begin, int32_t nshots, int64_t blocks, int32_t n,
                         hipStream_t s);
+// All nt steps of all shots in one cooperative (co-resident) launch with a
+// device-wide barrier per step.  `sync` = {arrival counter, error word}, both
+// zero at launch; the error word is set if a barrier wait exceeded
+// `spin_limit` polls.  At most max_per_cu blocks per CU are launched;
+// *grid_used receives the number of blocks.
+hipError_t launch_batch_persistent(int ndim, int order, int64_t nz_any, TileCfg cfg,
+                                   const ShotDesc* shots, const int64_t* begin, int32_t nshots,
+                                   int64_t items, int32_t nt, unsigned int* sync, int32_t spin_limit,
+                                   int max_per_cu, int* grid_used, hipStream_t s);
 // One pass over the model: per block {min m, min eta, count of invalid values}
 // into `partial` (3 * nblocks floats) for the host-side validation, and the
 // step coefficients alpha = dt^2/(m + eta dt/2), beta = (m - eta dt/2)/(m + eta dt/2).

@@ -46,73 +46,6 @@ __device__ __forceinline__ float sample_point(const SampleSet& s, const float* _
     return acc;
 }
 
-template <int DIM, int R, bool IMG>
-__global__ __launch_bounds__(kBlock) void k_step_naive(StepArgs a)
-{
-    const int64_t nz = a.nz, ny = a.ny, nx = a.nx;
-    const int64_t sy = nz, sx = ny * nz;
-    if ((int64_t)blockIdx.x >= a.stencil_blocks) {
-        const int64_t p = ((int64_t)blockIdx.x - a.stencil_blocks) * kBlock + threadIdx.x;
-        if (p < a.smp.npts) a.smp_out[p] = sample_point<DIM>(a.smp, a.cur, p, sy, sx);
-        return;
-    }
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= nx * sx) return;
-    const int64_t z = i % nz;
-    const int64_t rest = i / nz;
-    const int64_t y = rest % ny;
-    const int64_t x = rest / ny;
-    const float* __restrict__ u = a.cur;
-    const float u0 = u[i];
-    const float m2u0 = -2.f * u0;
-    float lap = 0.f;
-#pragma unroll
-    for (int j = 1; j <= R; ++j) {
-        const float p = (x + j < nx) ? u[i + j * sx] : 0.f;
-        const float m = (x - j >= 0) ? u[i - j * sx] : 0.f;
-        lap = fmaf(a.cx[j], (p + m) + m2u0, lap);
-    }
-    if (DIM == 3) {
-#pragma unroll
-        for (int j = 1; j <= R; ++j) {
-            const float p = (y + j < ny) ? u[i + j * sy] : 0.f;
-            const float m = (y - j >= 0) ? u[i - j * sy] : 0.f;
-            lap = fmaf(a.cy[j], (p + m) + m2u0, lap);
-        }
-    }
-#pragma unroll
-    for (int j = 1; j <= R; ++j) {
-        const float p = (z + j < nz) ? u[i + j] : 0.f;
-        const float m = (z - j >= 0) ? u[i - j] : 0.f;
-        lap = fmaf(a.cz[j], (p + m) + m2u0, lap);
-    }
-    const float prev = a.other[i];
-    const float al = a.alpha[i];
-    float v = fmaf(a.beta[i], u0 - prev, u0);
-    v = fmaf(al, lap, v);
-    if (a.inj_val) {
-        const int64_t row = x * ny + y;
-        const int32_t e0 = a.inj.row_ptr[row], e1 = a.inj.row_ptr[row + 1];
-        if (e0 != e1) {
-            float acc = 0.f;
-            bool hit = false;
-            for (int32_t e = e0; e < e1; ++e) {
-                const InjEntry en = a.inj.ent[e];
-                if (en.z == (int32_t)z) {
-                    acc = fmaf(en.w, a.inj_val[en.pt], acc);
-                    hit = true;
-                }
-            }
-            if (hit) v = fmaf(al, acc, v);
-        }
-    }
-    if (IMG) {
-        const float d2 = (prev + v) + m2u0;
-        a.img_grad[i] = fmaf(-a.img_fwd[i] * a.inv_dt2, d2, a.img_grad[i]);
-    }
-    a.out[i] = v;
-}
-
 // ---------------------------------------------------------------------------
 // 2.5D streaming step.  A block owns a (TY x TZ) tile of the (y, z) plane and
 // walks an x-chunk plane by plane.  Each thread keeps the 2R+1 x-neighbours of
@@ -286,6 +219,9 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
     }
 
     const int row_c = (ty + (DIM == 3 ? R : 0)) * PITCH + RZ + tz * VZ;
+    // does any injected node lie in this block's x-range? (uniform; most
+    // blocks of a forward run have none and skip the per-plane lookup)
+    const bool inj_any = a.inj_val && a.inj.row_ptr[xb * ny] != a.inj.row_ptr[xa * ny];
 
     // one plane; U is the position within the unrolled group of S planes
     auto plane = [&](auto UC, int64_t x) {
@@ -359,7 +295,7 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
             const float w = fmaf(P.be[v], c[v] - P.uo[v], c[v]);
             o[v] = fmaf(P.al[v], lap[v], w);
         }
-        if (a.inj_val) {
+        if (inj_any) {
             // planes without injected nodes skip the per-row lookup (uniform test)
             const int32_t* rp = a.inj.row_ptr;
             if (rp[(x + 1) * ny] != rp[x * ny] && own) {
@@ -458,6 +394,76 @@ __global__ __launch_bounds__(TZL* TY) void k_step_batch(const ShotDesc* __restri
 }
 
 
+// All nt steps of all shots in one persistent launch.  The grid is sized to
+// be co-resident (cooperative launch); block b takes items b, b + G, ... of
+// the flattened (shot, tile, x-chunk) list of each step, then the grid meets
+// at a barrier: a monotone arrival counter (step n completes at (n+1) G
+// arrivals) with agent-scope release/acquire fences so the next step sees
+// every block's writes.  Every wait is bounded: past `spin_limit` polls a
+// block raises the error word and the whole grid leaves at the next barrier,
+// so the launch always drains.
+template <int DIM, int R, int VZ, int TZL, int TY>
+__global__ __launch_bounds__(TZL* TY) void k_batch_persistent(const ShotDesc* __restrict__ shots,
+                                                             const int64_t* __restrict__ begin,
+                                                             int32_t nshots, int64_t items,
+                                                             int32_t nt, unsigned int* sync,
+                                                             int32_t spin_limit)
+{
+    for (int32_t n = 0; n < nt; ++n) {
+        for (int64_t b = blockIdx.x; b < items; b += gridDim.x) {
+            int lo = 0, hi = nshots - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (begin[mid] <= b) lo = mid;
+                else hi = mid - 1;
+            }
+            const ShotDesc& D = shots[lo];
+            StepArgs a = D.a;
+            float* even = D.buf[0];
+            float* odd = D.buf[1];
+            a.cur = (n & 1) ? odd : even;
+            a.other = (n & 1) ? even : odd;
+            a.out = (n & 1) ? even : odd;
+            a.inj_val = D.nsrc ? D.q + (int64_t)n * D.nsrc : nullptr;
+            a.smp_out = D.nrec ? D.d + (int64_t)n * D.nrec : nullptr;
+            const int64_t lb = b - begin[lo];
+            if (lb >= a.stencil_blocks) {
+                const int64_t p = (lb - a.stencil_blocks) * (TZL * TY) + threadIdx.x;
+                if (p < a.smp.npts && a.smp_out)
+                    a.smp_out[p] = sample_point<DIM>(a.smp, a.cur, p, a.nz, a.ny * a.nz);
+            } else {
+                stream_tile<DIM, R, VZ, TZL, TY, false>(a, lb);
+            }
+            __syncthreads();    // the next item rewrites the block's LDS tile
+        }
+        if (n + 1 == nt) break;
+        __shared__ int leave;
+        // every wave waits for its own stores to reach L2; then one thread per
+        // block releases them to the device (one L2 write-back per block, not
+        // per wave) and arrives
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            atomicAdd(&sync[0], 1u);
+            const unsigned int target = (unsigned int)(n + 1) * gridDim.x;
+            int spins = 0;
+            while (__hip_atomic_load(&sync[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (__hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > spin_limit) {
+                    atomicOr(&sync[1], 1u);
+                    break;
+                }
+            }
+            __threadfence();    // acquire: invalidates this CU's caches for the next step's reads
+            leave = __hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        }
+        __syncthreads();
+        if (leave) return;
+    }
+}
+
 template <int DIM_, int R_, int VZ_, int TZL_, int TY_>
 struct Cfg {
     static constexpr int DIM = DIM_, R = R_, VZ = VZ_, TZL = TZL_, TY = TY_;
@@ -522,39 +528,6 @@ int64_t plan_t(StepArgs& a, int xchunk)
     int64_t nsb = 0;
     if (a.smp_out && a.smp.npts > 0) nsb = (a.smp.npts + T::NT - 1) / T::NT;
     return a.stencil_blocks + nsb;
-}
-
-template <int DIM, int R>
-hipError_t launch_naive_t(const StepArgs& a0, hipStream_t s)
-{
-    StepArgs a = a0;
-    const int64_t n = a.nx * a.ny * a.nz;
-    a.stencil_blocks = (n + kBlock - 1) / kBlock;
-    int64_t nsb = 0;
-    if (a.smp_out && a.smp.npts > 0) nsb = (a.smp.npts + kBlock - 1) / kBlock;
-    else a.smp.npts = 0;
-    const int64_t blocks = a.stencil_blocks + nsb;
-    if (a.img_grad)
-        hipLaunchKernelGGL((k_step_naive<DIM, R, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_step_naive<DIM, R, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-}
-
-template <int DIM>
-hipError_t launch_naive_dim(int order, const StepArgs& a, hipStream_t s)
-{
-    switch (order) {
-    case 2: return launch_naive_t<DIM, 1>(a, s);
-    case 4: return launch_naive_t<DIM, 2>(a, s);
-    case 6: return launch_naive_t<DIM, 3>(a, s);
-    case 8: return launch_naive_t<DIM, 4>(a, s);
-    case 10: return launch_naive_t<DIM, 5>(a, s);
-    case 12: return launch_naive_t<DIM, 6>(a, s);
-    case 14: return launch_naive_t<DIM, 7>(a, s);
-    case 16: return launch_naive_t<DIM, 8>(a, s);
-    default: return hipErrorInvalidValue;
-    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_check_fields(const float* __restrict__ m,
@@ -775,10 +748,8 @@ int64_t plan_tiles(int ndim, int order, TileCfg cfg, StepArgs& a)
     return blocks;
 }
 
-hipError_t launch_step(int ndim, int order, const StepArgs& a0, hipStream_t s, int kernel,
-                       TileCfg cfg)
+hipError_t launch_step(int ndim, int order, const StepArgs& a0, hipStream_t s, TileCfg cfg)
 {
-    if (kernel == kNaive) return ndim == 2 ? launch_naive_dim<2>(order, a0, s) : launch_naive_dim<3>(order, a0, s);
     return with_cfg(ndim, order, cfg.variant, a0.nz, [&](auto C) {
         using CC = decltype(C);
         StepArgs a = a0;
@@ -791,6 +762,37 @@ hipError_t launch_step(int ndim, int order, const StepArgs& a0, hipStream_t s, i
             hipLaunchKernelGGL((k_step_stream<CC::DIM, CC::R, CC::VZ, CC::TZL, CC::TY, false>),
                                dim3((unsigned)blocks), dim3(CC::T::NT), 0, s, a);
         return hipGetLastError();
+    });
+}
+
+hipError_t launch_batch_persistent(int ndim, int order, int64_t nz_any, TileCfg cfg,
+                                   const ShotDesc* shots, const int64_t* begin, int32_t nshots,
+                                   int64_t items, int32_t nt, unsigned int* sync, int32_t spin_limit,
+                                   int max_per_cu, int* grid_used, hipStream_t s)
+{
+    return with_cfg(ndim, order, cfg.variant, nz_any, [&](auto C) {
+        using CC = decltype(C);
+        auto kern = k_batch_persistent<CC::DIM, CC::R, CC::VZ, CC::TZL, CC::TY>;
+        int dev = 0, per_cu = 0;
+        hipDeviceProp_t prop;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern),
+                                                             CC::T::NT, 0);
+        if (e != hipSuccess) return e;
+        // The occupancy figure is an upper bound that the dispatcher does not
+        // always reach for many small blocks; cap the grid at a few blocks per
+        // CU so that all of them are resident (the barrier needs every one).
+        if (per_cu > max_per_cu) per_cu = max_per_cu;
+        int64_t grid = (int64_t)per_cu * prop.multiProcessorCount;
+        if (grid > items) grid = items;
+        if (grid < 1) return hipErrorInvalidConfiguration;
+        *grid_used = (int)grid;
+        void* args[] = {(void*)&shots, (void*)&begin, (void*)&nshots, (void*)&items, (void*)&nt,
+                        (void*)&sync, (void*)&spin_limit};
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3((unsigned)grid),
+                                          dim3(CC::T::NT), args, 0, s);
     });
 }
 

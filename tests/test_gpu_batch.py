@@ -112,3 +112,19 @@ def test_tuner_picks_a_tile_and_results_stay_bitwise(dev):
     bt, bus = api.tune_batch(shots, steps=3)
     print(f"batch tile variant {bt >> 16} x-chunk {bt & 0xffff}: {bus:.2f} us/step", flush=True)
     assert bt > 0
+
+
+def test_persistent_batch_equals_per_step_batch_bitwise(dev):
+    """All steps of all shots in one persistent co-resident launch with a
+    device-wide barrier per step: bitwise the per-step result."""
+    import torch
+    from paper_1609_03361_amd import api
+    probs, shots = _shots(dev, n=5, nt=90)
+    a = api.forward_batch(shots, return_final=True)
+    b = api.forward_batch(shots, return_final=True, persistent=True)
+    mode = api.last_batch_mode()
+    torch.cuda.synchronize()
+    print(f"persistent batch ran in mode {mode}", flush=True)
+    assert mode == 2
+    for x, y in zip(a[0] + a[1], b[0] + b[1]):
+        assert torch.equal(x, y)

@@ -105,18 +105,3 @@ def test_cfl_and_field_errors(dev):
     with pytest.raises(_lib.WaveError) as e:
         api.forward(geom, m, neg, q)
     assert e.value.code == _lib.WAVE_EINVAL
-
-
-@pytest.mark.parametrize("shape,order", [((45, 38, 64), 8), ((33, 29, 20), 16), ((40, 37, 31), 4),
-                                         ((101, 101), 4), ((70, 129), 8)])
-def test_stream_kernel_equals_naive_kernel_bitwise(dev, shape, order, monkeypatch):
-    """Two independent kernels with the same per-point arithmetic order must agree bit for bit."""
-    import torch
-    from paper_1609_03361_amd import api
-    p = synth.random_problem(shape, order, 12, seed=17, nsrc=3, nrec=9)
-    geom, m, eta, q = device_inputs(p, dev)
-    a = api.forward(geom, m, eta, q, return_final=True)
-    monkeypatch.setenv("WAVE_STEP_KERNEL", "naive")
-    b = api.forward(geom, m, eta, q, return_final=True)
-    torch.cuda.synchronize()
-    assert torch.equal(a[1], b[1]) and torch.equal(a[0], b[0])

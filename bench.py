@@ -132,7 +132,7 @@ def batched_bench(dev, reps=2):
     tile, tune_us = api.tune_batch(shots, steps=10)
     pts = sum(p.npoints for p in probs) * probs[0].nt
 
-    def timed(fn):
+    def timed(fn, reps=reps):
         fn()
         torch.cuda.synchronize()
         best = float("inf")

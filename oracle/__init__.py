@@ -19,7 +19,7 @@ import numpy as np
 from .build import lib_path, build as _build
 
 __all__ = ["fd_weights", "sparse_weights", "laplacian", "forward", "adjoint", "gradient",
-           "num_threads", "OracleError"]
+           "diffusion", "num_threads", "OracleError"]
 
 _LIBS: dict = {}
 
@@ -54,6 +54,7 @@ def _lib(precision: str = "f64"):
                                        _D, _D]
         lib.oracle_gradient.argtypes = [C.POINTER(_Grid), _D, _D, C.c_int, _D, _D, C.c_int, _D,
                                         _D, _D, _D, _D, _D]
+        lib.oracle_diffusion.argtypes = [C.POINTER(_Grid), _D, _D, _D]
         lib.oracle_num_threads.restype = C.c_int
         lib.oracle_real_bytes.restype = C.c_int
         _LIBS[precision] = lib
@@ -196,3 +197,14 @@ def gradient(shape, spacing, order, dt, nt, m, eta, src, q, rec, d_obs, sbp=Fals
     if rc:
         raise OracleError(rc, "gradient")
     return {"grad": g, "grad_sbp": gs, "J": float(J[0]), "d": dsyn}
+
+
+def diffusion(shape, spacing, order, dt, nt, a, u0, precision="f64"):
+    """Forward-Euler diffusion u^{n+1} = u^n + dt a L u^n from u0; returns u^nt."""
+    N = int(np.prod(shape))
+    out = np.zeros(shape)
+    rc = _lib(precision).oracle_diffusion(C.byref(_grid(shape, spacing, order, dt, nt)),
+                                          _p(_f64(a, N)), _p(_f64(u0, N)), _p(out))
+    if rc:
+        raise OracleError(rc, "diffusion")
+    return out

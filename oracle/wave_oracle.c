@@ -524,3 +524,41 @@ out:
     free(uh); free(d);
     return rc;
 }
+
+/*
+ * Diffusion (Section "2D Diffusion Example", equation "eqn:diffusion"),
+ * forward Euler in time as in that section (time_order=1):
+ *   u^{n+1} = u^n + dt a L u^n
+ * with the same order-2k Laplacian and zero extension outside the grid.
+ * a is the (possibly spatially varying) diffusion coefficient.
+ */
+int oracle_diffusion(const oracle_grid *g, const double *a_in, const double *u0, double *u_final)
+{
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!a_in || !u0 || !u_final) return OR_EINVAL;
+    int64_t N = npoints(g), n3[3];
+    grid_dims(g, n3);
+    int k = g->order / 2;
+    real w[9];
+    load_weights(g->order, w);
+    real *u = (real *)malloc(sizeof(real) * N);
+    real *v = (real *)malloc(sizeof(real) * N);
+    real *a = (real *)malloc(sizeof(real) * N);
+    if (!u || !v || !a) { free(u); free(v); free(a); return OR_ENOMEM; }
+    for (int64_t p = 0; p < N; ++p) { u[p] = (real)u0[p]; a[p] = (real)a_in[p]; }
+    real dt = (real)g->dt;
+    for (int n = 0; n < g->nt; ++n) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n3[0]; ++i)
+            for (int64_t j = 0; j < n3[1]; ++j)
+                for (int64_t l = 0; l < n3[2]; ++l) {
+                    int64_t p = (i * n3[1] + j) * n3[2] + l;
+                    v[p] = u[p] + dt * a[p] * laplacian_at(u, g->shape, g->ndim, w, g->spacing, k, i, j, l);
+                }
+        real *t = u; u = v; v = t;
+    }
+    for (int64_t p = 0; p < N; ++p) u_final[p] = (double)u[p];
+    free(u); free(v); free(a);
+    return OR_OK;
+}

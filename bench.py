@@ -167,6 +167,27 @@ def batched_bench(dev, reps=2):
             "batched_vs_single": round(batched / single, 3)}
 
 
+def diffusion_bench(dev, reps=3):
+    """The paper's 2D diffusion example (1000 x 1000, spacing 0.001, order 2,
+    500 forward-Euler steps) on the step kernel."""
+    import torch
+    from paper_1609_03361_amd import api
+    n, h, alpha = 1000, 0.001, 0.5
+    dt = h ** 4 / (2 * alpha * 2 * h ** 2)
+    a = torch.full((n, n), alpha, device=dev)
+    u0 = torch.randn((n, n), device=dev)
+    api.diffusion((n, n), (h, h), 2, dt, 500, a, u0)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        api.diffusion((n, n), (h, h), 2, dt, 500, a, u0)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    return {"workload": "2D diffusion 1000x1000, order 2, 500 steps", "seconds": round(best, 5),
+            "gpts": round(n * n * 500 / best / 1e9, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,6 +282,7 @@ def main():
         out["fwi_gradient"] = gradient_bench(dev)
     if not args.no_batched:
         out["batched_shots"] = batched_bench(dev)
+        out["diffusion"] = diffusion_bench(dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -228,6 +228,19 @@ int wave_tune(const wave_grid* grid, const wave_opts* opts, int32_t steps, void*
 int wave_tune_batch(int32_t nshots, const wave_shot* shots, const wave_opts* opts, int32_t steps,
                     void* stream, int32_t* tile, double* us_per_step);
 
+/*
+ * Diffusion (Section "2D Diffusion Example", equation "eqn:diffusion"):
+ * u_t = a lap(u) with forward Euler in time, the same order-2k Laplacian and
+ * zero outside the grid, on the same step kernel (u^{n+1} = u^n + dt a L u^n).
+ *   a       [shape]  diffusion coefficient, finite, >= 0
+ *   u0      [shape]  initial state
+ *   u_final [shape]  receives u^nt
+ * Returns WAVE_ECFL when dt a_max max|lambda(L)| > 2.  Workspace: the size of
+ * WAVE_OP_FORWARD with no points.
+ */
+int wave_diffusion(const wave_grid* grid, const float* a, const float* u0, float* u_final,
+                   const wave_opts* opts, void* stream);
+
 /* Phase timing (a metrics aid).  With profiling on, each entry point called
  * by this thread records HIP events on its stream around its time loop(s),
  * from the first step launch to the last (set-up excluded).

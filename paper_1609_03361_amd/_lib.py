@@ -22,7 +22,8 @@ _NAMES = {0: "WAVE_OK", -1: "WAVE_EINVAL", -2: "WAVE_ECFL", -3: "WAVE_ERANGE",
 
 EXPORTS = ["wave_workspace_size", "wave_checkpoint_size", "wave_forward", "wave_adjoint",
            "wave_backward", "wave_gradient", "wave_batch_workspace_size", "wave_forward_batch",
-           "wave_tune", "wave_tune_batch", "wave_last_batch_mode", "wave_set_profiling",
+           "wave_tune", "wave_tune_batch", "wave_last_batch_mode", "wave_diffusion",
+           "wave_set_profiling",
            "wave_last_loop",
            "wave_last_error", "wave_version"]
 WAVE_FLAG_NO_GRAPH = 1
@@ -90,6 +91,8 @@ def lib():
         L.wave_last_loop.argtypes = [P(C.c_double), P(C.c_int64)]
         L.wave_last_loop.restype = C.c_int
         L.wave_last_batch_mode.restype = C.c_int
+        L.wave_diffusion.argtypes = [P(Grid), VP, VP, VP, P(Opts), VP]
+        L.wave_diffusion.restype = C.c_int
         L.wave_last_error.restype = C.c_char_p
         L.wave_version.restype = C.c_char_p
         _lib = L

@@ -20,7 +20,7 @@ import torch
 from . import _lib as L
 
 __all__ = ["Geometry", "forward", "adjoint", "backward", "gradient", "checkpoint_bytes",
-           "forward_batch", "tune", "tune_batch", "WaveFn", "wave_apply"]
+           "forward_batch", "tune", "tune_batch", "diffusion", "WaveFn", "wave_apply"]
 
 
 def _ptr(t):
@@ -243,6 +243,21 @@ def tune_batch(shots, steps: int = 10):
     L.check(L.lib().wave_tune_batch(B.n, B.arr, C.byref(o), int(steps), _stream(B.dev),
                                     C.byref(t), C.byref(us)), "wave_tune_batch")
     return int(t.value), float(us.value)
+
+
+def diffusion(shape, spacing, order, dt, nt, a, u0, tile=0):
+    """Forward-Euler diffusion u^{n+1} = u^n + dt a L u^n (the paper's diffusion
+    example) from u0 on the step kernel; returns u^nt."""
+    _need(a, "a", shape)
+    _need(u0, "u0", shape)
+    dev = a.device
+    grid = L.make_grid(shape, spacing, order, dt, nt)
+    empty = L.HostPoints(None, len(shape))
+    ws, o = _workspace(L.WAVE_OP_FORWARD, grid, empty, empty, dict(tile=tile), dev)
+    out = torch.empty(tuple(shape), dtype=torch.float32, device=dev)
+    L.check(L.lib().wave_diffusion(C.byref(grid), _ptr(a), _ptr(u0), _ptr(out), C.byref(o),
+                                   _stream(dev)), "wave_diffusion")
+    return out
 
 
 class WaveFn(torch.autograd.Function):

@@ -1362,4 +1362,67 @@ int wave_tune_batch(int32_t nshots, const wave_shot* shots, const wave_opts* opt
     }
 }
 
+
+int wave_diffusion(const wave_grid* grid, const float* a, const float* u0, float* u_final,
+                   const wave_opts* opts, void* stream)
+{
+    try {
+        Ctx C;
+        int rc = make_geo(grid, &C.G);
+        if (rc) return rc;
+        if (!a || !u0 || !u_final) return fail(WAVE_EINVAL, "a, u0 and u_final are required");
+        C.P = make_plan(WAVE_OP_FORWARD, C.G, 0, 0, opts);
+        if ((rc = check_ws(C.P, opts))) return rc;
+        C.ws = static_cast<char*>(opts->workspace);
+        C.s = static_cast<hipStream_t>(stream);
+        C.cfg = opts->tile > 0 ? tile_from_id(opts->tile) : cached_tile(tune_key(C.G));
+        set_weights(C);
+        const int64_t N = C.G.npts();
+        char* host = nullptr;
+        if ((rc = staging((size_t)kCheckBlocks * 2 * 4, &host))) return rc;
+        float* part = reinterpret_cast<float*>(host);
+        HIP_TRY(launch_diffusion_coef(a, N, C.at<float>(C.P.check), kCheckBlocks, C.at<float>(C.P.alpha),
+                                      C.at<float>(C.P.beta), (float)C.G.dt, C.s));
+        HIP_TRY(hipMemcpyAsync(part, C.at<float>(C.P.check), (size_t)kCheckBlocks * 2 * 4,
+                               hipMemcpyDeviceToHost, C.s));
+        HIP_TRY(hipEventRecord(g_stage.done, C.s));
+        HIP_TRY(hipStreamSynchronize(C.s));
+        float amax = 0.f, bad = 0.f;
+        for (int b = 0; b < kCheckBlocks; ++b) {
+            amax = std::max(amax, part[2 * b]);
+            bad += part[2 * b + 1];
+        }
+        if (bad > 0) return fail(WAVE_EINVAL, "%.0f entries of a are invalid (need finite, >= 0)", bad);
+        // forward Euler is stable while dt a max|lambda(L)| <= 2
+        double c[kMaxHalf + 1];
+        fd_weights(C.G.half, c);
+        double S = std::fabs(c[0]);
+        for (int j = 1; j <= C.G.half; ++j) S += 2.0 * std::fabs(c[j]);
+        double lam = 0;
+        for (int ax = 0; ax < 3; ++ax)
+            if (C.G.ndim == 3 || ax != 1) lam += S / (C.G.h[ax] * C.G.h[ax]);
+        if (C.G.dt * amax * lam > 2.0 * (1 + 1e-12))
+            return fail(WAVE_ECFL, "dt = %.9g exceeds the forward-Euler bound %.9g", C.G.dt,
+                        2.0 / (amax * lam));
+        float* buf[2] = {C.at<float>(C.P.wf[0]), C.at<float>(C.P.wf[1])};
+        HIP_TRY(hipMemcpyAsync(buf[0], u0, (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
+        HIP_TRY(launch_fill(buf[1], N, 0.f, C.s));
+        StepArgs sa = base_args(C);
+        if (prof_begin(C.s)) return fail(WAVE_EHIP, "profiling event failed");
+        for (int n = 0; n < C.G.nt; ++n) {
+            sa.cur = buf[n & 1];
+            sa.other = buf[(n + 1) & 1];     // multiplied by beta = 0; finite by construction
+            sa.out = buf[(n + 1) & 1];
+            HIP_TRY(step(C, sa));
+        }
+        if (prof_end(C.s)) return fail(WAVE_EHIP, "profiling event failed");
+        HIP_TRY(hipMemcpyAsync(u_final, buf[C.G.nt & 1], (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
+        return WAVE_OK;
+    } catch (const std::exception& e) {
+        return fail(WAVE_EINVAL, "exception: %s", e.what());
+    } catch (...) {
+        return fail(WAVE_EINVAL, "unknown exception");
+    }
+}
+
 }  // extern "C"

@@ -581,6 +581,40 @@ __global__ __launch_bounds__(kBlock) void k_fill(float* __restrict__ p, int64_t 
         p[i] = v;
 }
 
+// Diffusion set-up: per block {max a, count of invalid a} and the step
+// coefficients of forward Euler written in the leapfrog form of the step
+// kernel: alpha = dt a, beta = 0, so out = cur + dt a L cur.
+__global__ __launch_bounds__(kBlock) void k_diffusion_coef(const float* __restrict__ a, int64_t n,
+                                                           float* __restrict__ partial,
+                                                           float* __restrict__ alpha,
+                                                           float* __restrict__ beta, float dt)
+{
+    __shared__ float smax[kBlock], sbad[kBlock];
+    float mx = 0.f, bad = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const float v = a[i];
+        if (!(v >= 0.f) || !isfinite(v)) bad += 1.f;
+        else mx = fmaxf(mx, v);
+        alpha[i] = dt * v;
+        beta[i] = 0.f;
+    }
+    smax[threadIdx.x] = mx;
+    sbad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            smax[threadIdx.x] = fmaxf(smax[threadIdx.x], smax[threadIdx.x + w]);
+            sbad[threadIdx.x] += sbad[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x + 0] = smax[0];
+        partial[2 * blockIdx.x + 1] = sbad[0];
+    }
+}
+
 // r = d - d_obs and per-block partial sums of r^2 (grid-stride, fixed order).
 __global__ __launch_bounds__(kBlock) void k_residual(const float* __restrict__ d,
                                                      const float* __restrict__ dobs,
@@ -855,6 +889,14 @@ hipError_t launch_ckpt_decode(const unsigned short* in_u, const unsigned short* 
     else
         hipLaunchKernelGGL(k_ckpt_decode<false>, dim3(grid_for(n)), dim3(kBlock), 0, s, in_u, in_d,
                            sl, n, cur, prev);
+    return hipGetLastError();
+}
+
+hipError_t launch_diffusion_coef(const float* a, int64_t n, float* partial, int nblocks,
+                                 float* alpha, float* beta, float dt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_diffusion_coef, dim3(nblocks), dim3(kBlock), 0, s, a, n, partial, alpha,
+                       beta, dt);
     return hipGetLastError();
 }
 

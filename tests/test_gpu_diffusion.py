@@ -1,0 +1,59 @@
+"""Diffusion (the paper's 2D diffusion example) on the step kernel against
+the oracle's forward-Euler diffusion."""
+import numpy as np
+import pytest
+from scipy.ndimage import gaussian_filter
+
+import oracle
+from gpu_util import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(shape, spacing, order, dt, nt, a, u0):
+    import torch
+    from paper_1609_03361_amd import api
+    dev = torch.device("cuda:0")
+    out = api.diffusion(shape, spacing, order, dt, nt, torch.from_numpy(a).to(dev),
+                        torch.from_numpy(u0).to(dev))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def test_paper_example_1000x1000_500_steps():
+    """1000 x 1000, spacing 0.001, order 2, dt of equation eqn:diffusion_dt, 500 steps."""
+    n, h, alpha = 1000, 0.001, 0.5
+    dt = h ** 2 * h ** 2 / (2 * alpha * (h ** 2 + h ** 2))
+    rng = np.random.default_rng(1)
+    u0 = gaussian_filter(rng.standard_normal((n, n)), 4.0).astype(np.float32)
+    a = np.full((n, n), alpha, dtype=np.float32)
+    got = _run((n, n), (h, h), 2, dt, 500, a, u0)
+    ref = oracle.diffusion((n, n), (h, h), 2, dt, 500, a, u0)
+    err = rel_l2(got, ref)
+    print(f"diffusion 1000^2 x 500: rel L2 {err:.2e}", flush=True)
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("shape,order", [((40, 37, 52), 8), ((61, 75), 16)])
+def test_variable_coefficient(shape, order):
+    rng = np.random.default_rng(order)
+    spacing = tuple(rng.uniform(0.5, 1.5, len(shape)))
+    a = (0.5 + rng.uniform(0, 1, shape)).astype(np.float32)
+    u0 = gaussian_filter(rng.standard_normal(shape), 2.0).astype(np.float32)
+    c = oracle.fd_weights(order)
+    S = abs(c[0]) + 2 * np.sum(np.abs(c[1:]))
+    dt = 0.9 * 2.0 / (float(a.max()) * sum(S / h ** 2 for h in spacing))
+    got = _run(shape, spacing, order, dt, 60, a, u0)
+    ref = oracle.diffusion(shape, spacing, order, dt, 60, a, u0)
+    assert rel_l2(got, ref) < 1e-5
+
+
+def test_unstable_dt_is_rejected():
+    import torch
+    from paper_1609_03361_amd import api, _lib
+    n, h = 32, 0.01
+    a = torch.full((n, n), 1.0, device="cuda:0")
+    u0 = torch.zeros((n, n), device="cuda:0")
+    with pytest.raises(_lib.WaveError) as e:
+        api.diffusion((n, n), (h, h), 2, 1.01 * h * h / 4, 3, a, u0)
+    assert e.value.code == _lib.WAVE_ECFL

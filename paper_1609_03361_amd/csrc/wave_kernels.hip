@@ -145,6 +145,16 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
     const int64_t col = y * sy + z;
     const int64_t xa = chunk * a.xchunk;
     const int64_t xb = xa + a.xchunk < nx ? xa + a.xchunk : nx;
+    // Odd chunks walk x downwards: the 2R planes two neighbouring chunks both
+    // read are then read by both at the same time (at both ends, or at both
+    // starts), while they are in L2.  The stencil is symmetric in x and the
+    // pair sums commute, so the result does not depend on the direction.
+#ifndef WAVE_ALT_DIR
+#define WAVE_ALT_DIR 1
+#endif
+    const int dir = (WAVE_ALT_DIR && (chunk & 1)) ? -1 : 1;
+    const int64_t count = xb - xa;
+    const int64_t x0 = dir > 0 ? xa : xb - 1;
 
     // halo items of this thread: plane offset (or -1 when outside the grid) and LDS slot
     int64_t hoff[KH];
@@ -178,9 +188,10 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
         return r;
     };
 
+    // queue slot (U + R + j) % S holds plane x + dir j of the plane x at position U
     Vec<VZ> Q[S];
 #pragma unroll
-    for (int k = 0; k < 2 * R + 1; ++k) Q[k] = center(xa - R + k);
+    for (int k = 0; k < 2 * R + 1; ++k) Q[k] = center(x0 + dir * (k - R));
     Q[S - 1] = vzero<VZ>();
 
     // per-plane operands, double-buffered so plane x+1 is in flight while x is computed
@@ -196,7 +207,7 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
 #pragma unroll
         for (int k = 0; k < KH; ++k) {
             dst[k] = vzero<VZ>();
-            if (hoff[k] >= 0 && xx < nx) dst[k] = vload<VZ>(u + xx * sx + hoff[k]);
+            if (hoff[k] >= 0 && xx >= 0 && xx < nx) dst[k] = vload<VZ>(u + xx * sx + hoff[k]);
         }
     };
     auto fetch = [&](Pre& P, int64_t xx) {
@@ -212,10 +223,10 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
             P.be = vload_once<VZ, T::HINT>(a.beta + xx * sx + col);
         }
     };
-    if (xa < xb) fetch(pre0, xa);
+    if (count > 0) fetch(pre0, x0);
     if (T::LEAD) {
 #pragma unroll
-        for (int k = 0; k < HS; ++k) load_halo(hring[k], xa + k);
+        for (int k = 0; k < HS; ++k) load_halo(hring[k], k < count ? x0 + dir * k : -1);
     }
 
     const int row_c = (ty + (DIM == 3 ? R : 0)) * PITCH + RZ + tz * VZ;
@@ -224,12 +235,13 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
     const bool inj_any = a.inj_val && a.inj.row_ptr[xb * ny] != a.inj.row_ptr[xa * ny];
 
     // one plane; U is the position within the unrolled group of S planes
-    auto plane = [&](auto UC, int64_t x) {
+    auto plane = [&](auto UC, int64_t i) {
         constexpr int U = decltype(UC)::value;
         constexpr int B = U & 1;
+        const int64_t x = x0 + dir * i;
         Pre& P = B ? pre1 : pre0;
-        if (x + 1 < xb) fetch(B ? pre0 : pre1, x + 1);
-        Q[(U + 2 * R + 1) % S] = center(x + R + 1);
+        if (i + 1 < count) fetch(B ? pre0 : pre1, x + dir);
+        Q[(U + 2 * R + 1) % S] = center(x + dir * (R + 1));
         float* Ls = lds[B];
         const Vec<VZ> c = Q[(U + R) % S];
         vstore<VZ>(Ls + row_c, c);
@@ -238,7 +250,7 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
 #pragma unroll
             for (int k = 0; k < KH; ++k)
                 if (hlds[k] >= 0) vstore<VZ>(Ls + hlds[k], hr[k]);
-            if (x + R + 1 < xb) load_halo(hr, x + R + 1);
+            if (i + R + 1 < count) load_halo(hr, x + dir * (R + 1));
         } else {
 #pragma unroll
             for (int k = 0; k < KH; ++k)
@@ -336,10 +348,10 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
         }
     };
 
-    for (int64_t x = xa; x < xb; x += S) {
+    for (int64_t i = 0; i < count; i += S) {
         bool go = true;
         [&]<int... Us>(std::integer_sequence<int, Us...>) {
-            ((go = go && (x + Us < xb), go ? (plane(std::integral_constant<int, Us>{}, x + Us), 0) : 0), ...);
+            ((go = go && (i + Us < count), go ? (plane(std::integral_constant<int, Us>{}, i + Us), 0) : 0), ...);
         }(std::make_integer_sequence<int, S>{});
     }
 }

@@ -100,8 +100,10 @@ typedef enum {
 } wave_op;
 
 /* Bytes of workspace an entry point needs for this grid and point sets
- * (checkpoint storage is separate: wave_checkpoint_size).  Returns a
- * wave_status; *bytes is written on success. */
+ * (checkpoint storage is separate: wave_checkpoint_size).  Fields inside the
+ * workspace and the checkpoints use rows of nz rounded up to a multiple of 4
+ * points; caller arrays never do.  Returns a wave_status; *bytes is written
+ * on success. */
 int wave_workspace_size(int32_t op, const wave_grid* grid, const wave_points* src,
                         const wave_points* rec, const wave_opts* opts, size_t* bytes);
 
@@ -185,9 +187,8 @@ int wave_gradient(const wave_grid* grid, const float* m, const float* eta,
  * launch over a flattened list of (shot, tile, x-chunk) blocks, and the nt
  * launches are captured once into a hipGraph that is replayed (and reused by
  * later calls with the same buffers).  Shots may differ in shape, spacing,
- * fields and points; they must share ndim, space_order, nt and dt (3D: also
- * whether nz is a multiple of 4).  Each shot's results are bitwise those of
- * wave_forward on the same shot.
+ * fields and points; they must share ndim, space_order, nt and dt.  Each
+ * shot's results are bitwise those of wave_forward on the same shot.
  */
 typedef struct {
     wave_grid grid;

@@ -83,7 +83,15 @@ struct Geo {
     int64_t n[3] = {0, 0, 0};     // 3D view: (nx, ny, nz); 2D: (nx, 1, nz)
     double h[3] = {0, 0, 0};      // spacing in the 3D view (2D: hy unused)
     double dt = 0;
+    // Fields inside the library (coefficients, wavefields, checkpoints,
+    // gradient accumulator) use rows of nzp = nz rounded up to a multiple of
+    // 4, so that every row starts 16-byte aligned and the step kernel can
+    // load four z-points per lane.  The padding points hold alpha = beta = 0
+    // and wavefield values 0, which the update keeps at 0, so to the stencil
+    // they are the zero halo outside the grid.  Caller arrays are unpadded.
+    int64_t nzp = 0;
     int64_t npts() const { return n[0] * n[1] * n[2]; }
+    int64_t npad() const { return n[0] * n[1] * nzp; }
     int64_t nrows() const { return n[0] * n[1]; }
 };
 
@@ -112,11 +120,30 @@ int make_geo(const wave_grid* g, Geo* G)
         G->n[0] = g->shape[0]; G->n[1] = 1; G->n[2] = g->shape[1];
         G->h[0] = g->spacing[0]; G->h[1] = 1.0; G->h[2] = g->spacing[1];
     }
-    const double total = (double)G->n[0] * (double)G->n[1] * (double)G->n[2];
+    G->nzp = (G->n[2] + 3) / 4 * 4;
+    const double total = (double)G->n[0] * (double)G->n[1] * (double)G->nzp;
     if (total > 4.0e10) return fail(WAVE_EINVAL, "grid has too many points");
     if ((double)G->n[0] * (double)G->n[1] >= 2147483647.0)
         return fail(WAVE_EINVAL, "nx * ny must be below 2^31");
     return WAVE_OK;
+}
+
+// Caller arrays [rows][nz] <-> library fields [rows][nzp].
+hipError_t copy_out(float* dst, const float* src, const Geo& G, hipStream_t s)
+{
+    if (G.nzp == G.n[2])
+        return hipMemcpyAsync(dst, src, (size_t)G.npts() * 4, hipMemcpyDeviceToDevice, s);
+    return hipMemcpy2DAsync(dst, (size_t)G.n[2] * 4, src, (size_t)G.nzp * 4, (size_t)G.n[2] * 4,
+                            (size_t)G.nrows(), hipMemcpyDeviceToDevice, s);
+}
+
+// The padding of dst must already be zero.
+hipError_t copy_in(float* dst, const float* src, const Geo& G, hipStream_t s)
+{
+    if (G.nzp == G.n[2])
+        return hipMemcpyAsync(dst, src, (size_t)G.npts() * 4, hipMemcpyDeviceToDevice, s);
+    return hipMemcpy2DAsync(dst, (size_t)G.nzp * 4, src, (size_t)G.n[2] * 4, (size_t)G.n[2] * 4,
+                            (size_t)G.nrows(), hipMemcpyDeviceToDevice, s);
 }
 
 // Central second-derivative weights of order 2k (Section "High-level API":
@@ -193,7 +220,7 @@ int make_points(const Geo& G, const wave_points* P, const char* what, HostPoints
             i0[A] = i;
             f[A] = x - (double)i;
         }
-        out->base[p] = (i0[0] * G.n[1] + i0[1]) * G.n[2] + i0[2];
+        out->base[p] = (i0[0] * G.n[1] + i0[1]) * G.nzp + i0[2];
         for (int A = 0; A < 3; ++A) out->cell[(size_t)p * 3 + A] = i0[A];
         for (int c = 0; c < nc; ++c) {
             double w = 1.0;
@@ -283,7 +310,7 @@ size_t ckpt_bytes(const Geo& G, const wave_opts* o)
 {
     const int K = ckpt_every(o);
     const int64_t nck = (G.nt + K - 1) / K;
-    const size_t snap = round_up((size_t)G.npts() * ckpt_elem(o), kAlign);
+    const size_t snap = round_up((size_t)G.npad() * ckpt_elem(o), kAlign);
     return (size_t)nck * 2 * snap + round_up((size_t)nck * 4 * sizeof(float), kAlign);
 }
 
@@ -291,7 +318,7 @@ Plan make_plan(int op, const Geo& G, int nsrc, int nrec, const wave_opts* o)
 {
     Plan P;
     Carver c;
-    const size_t N = (size_t)G.npts();
+    const size_t N = (size_t)G.npad();
     const int nc = 1 << G.ndim;
     P.alpha = c.take(N * 4);
     P.beta = c.take(N * 4);
@@ -500,9 +527,9 @@ int setup(Ctx& C, int op, const wave_grid* grid, const float* m, const float* et
         HIP_TRY(hipMemcpyAsync(C.ws + u.dst, host + off, u.bytes, hipMemcpyHostToDevice, C.s));
         off += round_up(u.bytes, 64);
     }
-    const int64_t N = C.G.npts();
-    HIP_TRY(launch_check_fields(m, eta, N, C.at<float>(C.P.check), kCheckBlocks,
-                                C.at<float>(C.P.alpha), C.at<float>(C.P.beta), (float)C.G.dt, C.s));
+    HIP_TRY(launch_check_fields(m, eta, C.G.nrows(), C.G.n[2], C.G.nzp, C.at<float>(C.P.check),
+                                kCheckBlocks, C.at<float>(C.P.alpha), C.at<float>(C.P.beta),
+                                (float)C.G.dt, C.s));
     HIP_TRY(hipMemcpyAsync(part, C.at<float>(C.P.check), part_bytes, hipMemcpyDeviceToHost, C.s));
     HIP_TRY(hipEventRecord(g_stage.done, C.s));
     HIP_TRY(hipStreamSynchronize(C.s));
@@ -527,7 +554,7 @@ StepArgs base_args(const Ctx& C)
     std::memset(&a, 0, sizeof a);
     a.alpha = C.at<float>(C.P.alpha);
     a.beta = C.at<float>(C.P.beta);
-    a.nx = C.G.n[0]; a.ny = C.G.n[1]; a.nz = C.G.n[2];
+    a.nx = C.G.n[0]; a.ny = C.G.n[1]; a.nz = C.G.nzp;
     std::memcpy(a.cx, C.cx, sizeof a.cx);
     std::memcpy(a.cy, C.cy, sizeof a.cy);
     std::memcpy(a.cz, C.cz, sizeof a.cz);
@@ -576,13 +603,13 @@ CkptView ckpt_view(const Geo& G, const wave_opts* o, void* base)
     v.elem = ckpt_elem(o);
     v.dtype = o ? o->ckpt_dtype : WAVE_CKPT_FP32;
     v.nck = (G.nt + v.K - 1) / v.K;
-    v.snap = round_up((size_t)G.npts() * v.elem, kAlign);
+    v.snap = round_up((size_t)G.npad() * v.elem, kAlign);
     return v;
 }
 
 int store_checkpoint(const Ctx& C, const CkptView& v, int c, const float* cur, const float* prev)
 {
-    const int64_t N = C.G.npts();
+    const int64_t N = C.G.npad();
     if (v.dtype == WAVE_CKPT_FP32) {
         HIP_TRY(hipMemcpyAsync(v.snapshot(c, 0), cur, (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
         HIP_TRY(hipMemcpyAsync(v.snapshot(c, 1), prev, (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
@@ -596,7 +623,7 @@ int store_checkpoint(const Ctx& C, const CkptView& v, int c, const float* cur, c
 
 int load_checkpoint(const Ctx& C, const CkptView& v, int c, float* cur, float* prev)
 {
-    const int64_t N = C.G.npts();
+    const int64_t N = C.G.npad();
     if (v.dtype == WAVE_CKPT_FP32) {
         HIP_TRY(hipMemcpyAsync(cur, v.snapshot(c, 0), (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
         HIP_TRY(hipMemcpyAsync(prev, v.snapshot(c, 1), (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
@@ -613,7 +640,7 @@ int load_checkpoint(const Ctx& C, const CkptView& v, int c, float* cur, float* p
 int run_forward(const Ctx& C, const float* q, float* d, float* u_final, const CkptView* ck,
                 bool close_prof)
 {
-    const int64_t N = C.G.npts();
+    const int64_t N = C.G.npad();
     float* buf[2] = {C.at<float>(C.P.wf[0]), C.at<float>(C.P.wf[1])};
     HIP_TRY(launch_fill(buf[0], N, 0.f, C.s));
     HIP_TRY(launch_fill(buf[1], N, 0.f, C.s));
@@ -635,8 +662,7 @@ int run_forward(const Ctx& C, const float* q, float* d, float* u_final, const Ck
         cur = 1 - cur;
     }
     if (close_prof && prof_end(C.s)) return fail(WAVE_EHIP, "profiling event failed");
-    if (u_final)
-        HIP_TRY(hipMemcpyAsync(u_final, buf[cur], (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
+    if (u_final) HIP_TRY(copy_out(u_final, buf[cur], C.G, C.s));
     return WAVE_OK;
 }
 
@@ -645,7 +671,7 @@ int run_forward(const Ctx& C, const float* q, float* d, float* u_final, const Ck
 int run_backward(const Ctx& C, const float* q, const float* r, const CkptView& ck, float* grad,
                  float* grad_q, bool open_prof)
 {
-    const int64_t N = C.G.npts();
+    const int64_t N = C.G.npad();
     const int nt = C.G.nt;
     float* v[2] = {C.at<float>(C.P.adj[0]), C.at<float>(C.P.adj[1])};
     HIP_TRY(launch_fill(v[0], N, 0.f, C.s));
@@ -687,7 +713,7 @@ int run_backward(const Ctx& C, const float* q, const float* r, const CkptView& c
         }
     }
     if (prof_end(C.s)) return fail(WAVE_EHIP, "profiling event failed");
-    HIP_TRY(hipMemcpyAsync(grad, gacc, (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
+    HIP_TRY(copy_out(grad, gacc, C.G, C.s));
     return WAVE_OK;
 }
 
@@ -762,8 +788,6 @@ int batch_plan(int32_t nshots, const wave_shot* shots, BatchPlan* B, bool build_
         const Geo& G0 = B->shots[0].G;
         if (S.G.ndim != G0.ndim || S.G.order != G0.order || S.G.nt != G0.nt || S.G.dt != G0.dt)
             return fail(WAVE_EINVAL, "shot %d: every shot needs the same ndim, space_order, nt and dt", i);
-        if (S.G.ndim == 3 && (S.G.n[2] % 4 == 0) != (G0.n[2] % 4 == 0))
-            return fail(WAVE_EINVAL, "shot %d: 3D shots must all have nz %% 4 == 0 or all not", i);
         if (!shots[i].m) return fail(WAVE_EINVAL, "shot %d: m is NULL", i);
         if (shots[i].src.npts > 0 && !shots[i].q) return fail(WAVE_EINVAL, "shot %d: q is NULL", i);
         if (shots[i].rec.npts > 0 && !shots[i].d) return fail(WAVE_EINVAL, "shot %d: d is NULL", i);
@@ -775,7 +799,7 @@ int batch_plan(int32_t nshots, const wave_shot* shots, BatchPlan* B, bool build_
         }
         const int ns = shots[i].src.npts > 0 ? shots[i].src.npts : 0;
         const int nr = shots[i].rec.npts > 0 ? shots[i].rec.npts : 0;
-        const size_t N = (size_t)S.G.npts();
+        const size_t N = (size_t)S.G.npad();
         const int nc = 1 << S.G.ndim;
         S.alpha = c.take(N * 4);
         S.beta = c.take(N * 4);
@@ -796,7 +820,7 @@ StepArgs shot_args(const BatchShot& S, char* ws)
     std::memset(&a, 0, sizeof a);
     a.alpha = reinterpret_cast<float*>(ws + S.alpha);
     a.beta = reinterpret_cast<float*>(ws + S.beta);
-    a.nx = S.G.n[0]; a.ny = S.G.n[1]; a.nz = S.G.n[2];
+    a.nx = S.G.n[0]; a.ny = S.G.n[1]; a.nz = S.G.nzp;
     double c[kMaxHalf + 1];
     fd_weights(S.G.half, c);
     for (int j = 1; j <= S.G.half; ++j) {
@@ -876,7 +900,7 @@ int batch_setup(const BatchPlan& B, const wave_shot* shots, char* ws, hipStream_
     float* part = reinterpret_cast<float*>(host);
     for (int i = 0; i < n; ++i) {
         const BatchShot& S = B.shots[i];
-        HIP_TRY(launch_check_fields(shots[i].m, shots[i].eta, S.G.npts(),
+        HIP_TRY(launch_check_fields(shots[i].m, shots[i].eta, S.G.nrows(), S.G.n[2], S.G.nzp,
                                     reinterpret_cast<float*>(ws + B.check) + (size_t)i * kCheckBlocksShot * 3,
                                     kCheckBlocksShot, reinterpret_cast<float*>(ws + S.alpha),
                                     reinterpret_cast<float*>(ws + S.beta), (float)S.G.dt, st));
@@ -898,8 +922,8 @@ int batch_setup(const BatchPlan& B, const wave_shot* shots, char* ws, hipStream_
     }
     for (int i = 0; i < n; ++i) {
         const BatchShot& S = B.shots[i];
-        HIP_TRY(launch_fill(reinterpret_cast<float*>(ws + S.buf0), S.G.npts(), 0.f, st));
-        HIP_TRY(launch_fill(reinterpret_cast<float*>(ws + S.buf1), S.G.npts(), 0.f, st));
+        HIP_TRY(launch_fill(reinterpret_cast<float*>(ws + S.buf0), S.G.npad(), 0.f, st));
+        HIP_TRY(launch_fill(reinterpret_cast<float*>(ws + S.buf1), S.G.npad(), 0.f, st));
     }
     return WAVE_OK;
 }
@@ -961,7 +985,7 @@ int run_batch_persistent(const BatchPlan& B, char* ws, TileCfg cfg, int64_t item
     // can be resident at once, which the device-wide barrier relies on
     int per_cu = 4;
     if (const char* e = std::getenv("WAVE_PERSISTENT_BLOCKS_PER_CU")) per_cu = std::max(1, std::atoi(e));
-    HIP_TRY(launch_batch_persistent(G.ndim, G.order, G.n[2], cfg, d_desc, d_begin, nshots, items,
+    HIP_TRY(launch_batch_persistent(G.ndim, G.order, G.nzp, cfg, d_desc, d_begin, nshots, items,
                                     G.nt, sync, spin_limit, per_cu, &grid, st));
     g_batch_mode = 2;
     unsigned int words[2] = {0, 0};
@@ -985,7 +1009,7 @@ int run_batch_loop(const BatchPlan& B, char* ws, TileCfg cfg, int64_t blocks, hi
     if (!use_graph) {
         for (int n = 0; n < G.nt; ++n) {
             ++g_prof.launches;
-            HIP_TRY(launch_batch(G.ndim, G.order, G.n[2], cfg, d_desc, d_begin, nshots, blocks, n, st));
+            HIP_TRY(launch_batch(G.ndim, G.order, G.nzp, cfg, d_desc, d_begin, nshots, blocks, n, st));
         }
         return WAVE_OK;
     }
@@ -995,7 +1019,7 @@ int run_batch_loop(const BatchPlan& B, char* ws, TileCfg cfg, int64_t blocks, hi
         char* k = key.data();
         auto put = [&](const void* p, size_t n) { std::memcpy(k, p, n); k += n; };
         put(&d_desc, sizeof(void*)); put(&d_begin, sizeof(void*));
-        put(&blocks, sizeof(int64_t)); int64_t nz = G.n[2]; put(&nz, sizeof(int64_t));
+        put(&blocks, sizeof(int64_t)); int64_t nz = G.nzp; put(&nz, sizeof(int64_t));
         int v[6] = {nshots, G.nt, G.ndim, G.order, cfg.variant, cfg.xchunk};
         put(v, sizeof v);
     }
@@ -1005,7 +1029,7 @@ int run_batch_loop(const BatchPlan& B, char* ws, TileCfg cfg, int64_t blocks, hi
         HIP_TRY(hipStreamBeginCapture(g_graph.capture, hipStreamCaptureModeThreadLocal));
         hipError_t err = hipSuccess;
         for (int n = 0; n < G.nt && err == hipSuccess; ++n)
-            err = launch_batch(G.ndim, G.order, G.n[2], cfg, d_desc, d_begin, nshots, blocks, n,
+            err = launch_batch(G.ndim, G.order, G.nzp, cfg, d_desc, d_begin, nshots, blocks, n,
                                g_graph.capture);
         hipGraph_t graph = nullptr;
         const hipError_t e2 = hipStreamEndCapture(g_graph.capture, &graph);
@@ -1119,7 +1143,7 @@ int wave_adjoint(const wave_grid* grid, const float* m, const float* eta, const 
         if (rec && rec->npts > 0 && !d) return fail(WAVE_EINVAL, "d is NULL with %d receivers", rec->npts);
         int rc = setup(C, WAVE_OP_ADJOINT, grid, m, eta, src, rec, opts, stream);
         if (rc) return rc;
-        const int64_t N = C.G.npts();
+        const int64_t N = C.G.npad();
         float* v[2] = {C.at<float>(C.P.adj[0]), C.at<float>(C.P.adj[1])};
         HIP_TRY(launch_fill(v[0], N, 0.f, C.s));
         HIP_TRY(launch_fill(v[1], N, 0.f, C.s));
@@ -1139,7 +1163,7 @@ int wave_adjoint(const wave_grid* grid, const float* m, const float* eta, const 
         if (prof_end(C.s)) return fail(WAVE_EHIP, "profiling event failed");
         // v[1 - vc] holds v^0 (the state sampled last)
         if (v_final)
-            HIP_TRY(hipMemcpyAsync(v_final, v[1 - vc], (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
+            HIP_TRY(copy_out(v_final, v[1 - vc], C.G, C.s));
         return WAVE_OK;
     } catch (const std::exception& e) {
         return fail(WAVE_EINVAL, "exception: %s", e.what());
@@ -1245,8 +1269,8 @@ int wave_forward_batch(int32_t nshots, const wave_shot* shots, const wave_opts* 
         for (int i = 0; i < nshots; ++i)
             if (shots[i].u_final) {
                 const BatchShot& S = B.shots[i];
-                HIP_TRY(hipMemcpyAsync(shots[i].u_final, ws + (last ? S.buf1 : S.buf0),
-                                       (size_t)S.G.npts() * 4, hipMemcpyDeviceToDevice, st));
+                HIP_TRY(copy_out(shots[i].u_final,
+                                 reinterpret_cast<const float*>(ws + (last ? S.buf1 : S.buf0)), S.G, st));
             }
         return WAVE_OK;
     } catch (const std::exception& e) {
@@ -1269,7 +1293,7 @@ int wave_tune(const wave_grid* grid, const wave_opts* opts, int32_t steps, void*
         C.ws = static_cast<char*>(opts->workspace);
         C.s = static_cast<hipStream_t>(stream);
         set_weights(C);
-        const int64_t N = C.G.npts();
+        const int64_t N = C.G.npad();
         for (size_t off : {C.P.alpha, C.P.beta, C.P.wf[0], C.P.wf[1]})
             HIP_TRY(launch_fill(C.at<float>(off), N, 0.f, C.s));
         StepArgs a = base_args(C);
@@ -1280,7 +1304,7 @@ int wave_tune(const wave_grid* grid, const wave_opts* opts, int32_t steps, void*
         HIP_TRY(hipEventCreate(&ev.b));
         double best = 1e300;
         TileCfg best_cfg;
-        for (const TileCfg& cfg : tile_candidates(C.G.ndim, C.G.half, C.G.n[0], C.G.n[2])) {
+        for (const TileCfg& cfg : tile_candidates(C.G.ndim, C.G.half, C.G.n[0], C.G.nzp)) {
             for (int w = 0; w < 2; ++w) HIP_TRY(launch_step(C.G.ndim, C.G.order, a, C.s, cfg));
             double t = 1e300;
             for (int rep = 0; rep < 3; ++rep) {
@@ -1329,7 +1353,7 @@ int wave_tune_batch(int32_t nshots, const wave_shot* shots, const wave_opts* opt
         TileCfg best_cfg;
         const ShotDesc* d_desc = reinterpret_cast<const ShotDesc*>(ws + B.desc);
         const int64_t* d_begin = reinterpret_cast<const int64_t*>(ws + B.begin);
-        for (const TileCfg& cfg : tile_candidates(G.ndim, G.half, maxnx, G.n[2])) {
+        for (const TileCfg& cfg : tile_candidates(G.ndim, G.half, maxnx, G.nzp)) {
             std::vector<ShotDesc> desc;
             std::vector<int64_t> begin;
             int64_t blocks = 0;
@@ -1337,12 +1361,12 @@ int wave_tune_batch(int32_t nshots, const wave_shot* shots, const wave_opts* opt
             for (ShotDesc& D : desc) { D.nsrc = 0; D.nrec = 0; D.d = nullptr; }   // no outputs touched
             if ((rc = upload_descs(desc, begin, ws, B, st))) return rc;
             for (int w = 0; w < 2; ++w)
-                HIP_TRY(launch_batch(G.ndim, G.order, G.n[2], cfg, d_desc, d_begin, nshots, blocks, w, st));
+                HIP_TRY(launch_batch(G.ndim, G.order, G.nzp, cfg, d_desc, d_begin, nshots, blocks, w, st));
             double t = 1e300;
             for (int rep = 0; rep < 3; ++rep) {
                 HIP_TRY(hipEventRecord(ev.a, st));
                 for (int i = 0; i < steps; ++i)
-                    HIP_TRY(launch_batch(G.ndim, G.order, G.n[2], cfg, d_desc, d_begin, nshots, blocks, i, st));
+                    HIP_TRY(launch_batch(G.ndim, G.order, G.nzp, cfg, d_desc, d_begin, nshots, blocks, i, st));
                 HIP_TRY(hipEventRecord(ev.b, st));
                 HIP_TRY(hipEventSynchronize(ev.b));
                 float ms = 0.f;
@@ -1377,12 +1401,13 @@ int wave_diffusion(const wave_grid* grid, const float* a, const float* u0, float
         C.s = static_cast<hipStream_t>(stream);
         C.cfg = opts->tile > 0 ? tile_from_id(opts->tile) : cached_tile(tune_key(C.G));
         set_weights(C);
-        const int64_t N = C.G.npts();
+        const int64_t N = C.G.npad();
         char* host = nullptr;
         if ((rc = staging((size_t)kCheckBlocks * 2 * 4, &host))) return rc;
         float* part = reinterpret_cast<float*>(host);
-        HIP_TRY(launch_diffusion_coef(a, N, C.at<float>(C.P.check), kCheckBlocks, C.at<float>(C.P.alpha),
-                                      C.at<float>(C.P.beta), (float)C.G.dt, C.s));
+        HIP_TRY(launch_diffusion_coef(a, C.G.nrows(), C.G.n[2], C.G.nzp, C.at<float>(C.P.check),
+                                      kCheckBlocks, C.at<float>(C.P.alpha), C.at<float>(C.P.beta),
+                                      (float)C.G.dt, C.s));
         HIP_TRY(hipMemcpyAsync(part, C.at<float>(C.P.check), (size_t)kCheckBlocks * 2 * 4,
                                hipMemcpyDeviceToHost, C.s));
         HIP_TRY(hipEventRecord(g_stage.done, C.s));
@@ -1405,7 +1430,8 @@ int wave_diffusion(const wave_grid* grid, const float* a, const float* u0, float
             return fail(WAVE_ECFL, "dt = %.9g exceeds the forward-Euler bound %.9g", C.G.dt,
                         2.0 / (amax * lam));
         float* buf[2] = {C.at<float>(C.P.wf[0]), C.at<float>(C.P.wf[1])};
-        HIP_TRY(hipMemcpyAsync(buf[0], u0, (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
+        if (C.G.nzp != C.G.n[2]) HIP_TRY(launch_fill(buf[0], N, 0.f, C.s));
+        HIP_TRY(copy_in(buf[0], u0, C.G, C.s));
         HIP_TRY(launch_fill(buf[1], N, 0.f, C.s));
         StepArgs sa = base_args(C);
         if (prof_begin(C.s)) return fail(WAVE_EHIP, "profiling event failed");
@@ -1416,7 +1442,7 @@ int wave_diffusion(const wave_grid* grid, const float* a, const float* u0, float
             HIP_TRY(step(C, sa));
         }
         if (prof_end(C.s)) return fail(WAVE_EHIP, "profiling event failed");
-        HIP_TRY(hipMemcpyAsync(u_final, buf[C.G.nt & 1], (size_t)N * 4, hipMemcpyDeviceToDevice, C.s));
+        HIP_TRY(copy_out(u_final, buf[C.G.nt & 1], C.G, C.s));
         return WAVE_OK;
     } catch (const std::exception& e) {
         return fail(WAVE_EINVAL, "exception: %s", e.what());

@@ -80,7 +80,8 @@ struct TileCfg {
 inline TileCfg tile_from_id(int id) { TileCfg c; c.variant = (id >> 16) & 0xff; c.xchunk = id & 0xffff; return c; }
 inline int tile_id(const TileCfg& c) { return (c.variant << 16) | c.xchunk; }
 
-// Number of block-shape variants for a grid (2D: 3; 3D with nz % 4 == 0: 3; else 1).
+// Number of block-shape variants for a grid (3 for every grid; the row length
+// handed to the kernels is always a multiple of 4).
 int tile_variants(int ndim, int64_t nz);
 // Fill the tiling fields of `a` (ntz, nty, xchunk, stencil_blocks, remap) for
 // `cfg`; returns the block count of one launch including receiver samplers.
@@ -105,13 +106,17 @@ hipError_t launch_batch_persistent(int ndim, int order, int64_t nz_any, TileCfg 
 // One pass over the model: per block {min m, min eta, count of invalid values}
 // into `partial` (3 * nblocks floats) for the host-side validation, and the
 // step coefficients alpha = dt^2/(m + eta dt/2), beta = (m - eta dt/2)/(m + eta dt/2).
-hipError_t launch_check_fields(const float* m, const float* eta, int64_t n, float* partial,
-                               int nblocks, float* alpha, float* beta, float dt, hipStream_t s);
+// m and eta are [rows][nz]; alpha and beta are written as [rows][nzp] with
+// zeros in the padding columns nz <= z < nzp.
+hipError_t launch_check_fields(const float* m, const float* eta, int64_t rows, int64_t nz,
+                               int64_t nzp, float* partial, int nblocks, float* alpha, float* beta,
+                               float dt, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
 // Diffusion coefficients alpha = dt a, beta = 0 and per block {max a, invalid count}
-// into `partial` (2 * nblocks floats).
-hipError_t launch_diffusion_coef(const float* a, int64_t n, float* partial, int nblocks,
-                                 float* alpha, float* beta, float dt, hipStream_t s);
+// into `partial` (2 * nblocks floats); a is [rows][nz], alpha and beta [rows][nzp].
+hipError_t launch_diffusion_coef(const float* a, int64_t rows, int64_t nz, int64_t nzp,
+                                 float* partial, int nblocks, float* alpha, float* beta, float dt,
+                                 hipStream_t s);
 // Reduced-precision checkpoint of (cur, prev): stores cur and cur - prev as
 // BF16 (bf16 != 0) or FP16 with per-array power-of-two scales kept in `slot`
 // (4 words: scale_u, scale_d, and two reduction words).

@@ -482,23 +482,23 @@ struct Cfg {
     using T = Tile<DIM_, R_, VZ_, TZL_, TY_>;
 };
 
-// Block shapes: 2D (scalar lanes along z): 256, 128 or 64 z-points per block;
-// 3D with nz % 4 == 0 (four z-points per lane): 64 z x 16 rows, 64 z x 8 rows
-// or 32 z x 32 rows; other 3D grids: 64 scalar lanes x 4 rows.
+// Block shapes.  The row length nz is a multiple of 4 (the library pads its
+// fields), so every row starts 16-byte aligned.  2D: one wave with four
+// z-points per lane (256 z), 128 scalar lanes (128 z) or one wave with two
+// z-points per lane (128 z); 3D (four z-points per lane): 64 z x 16 rows,
+// 64 z x 8 rows or 32 z x 32 rows.
 template <int DIM, int R, class F>
 hipError_t with_shape(int variant, int64_t nz, F&& f)
 {
+    if (nz % 4 != 0) return hipErrorInvalidValue;
     if constexpr (DIM == 2) {
         if (variant == 1) return f(Cfg<2, R, 1, 128, 1>{});
-        if (variant == 2) return f(Cfg<2, R, 1, 64, 1>{});
-        return f(Cfg<2, R, 1, 256, 1>{});
+        if (variant == 2) return f(Cfg<2, R, 2, 64, 1>{});
+        return f(Cfg<2, R, 4, 64, 1>{});
     } else {
-        if (nz % 4 == 0) {
-            if (variant == 1) return f(Cfg<3, R, 4, 16, 8>{});
-            if (variant == 2) return f(Cfg<3, R, 4, 8, 32>{});
-            return f(Cfg<3, R, 4, 16, 16>{});
-        }
-        return f(Cfg<3, R, 1, 64, 4>{});
+        if (variant == 1) return f(Cfg<3, R, 4, 16, 8>{});
+        if (variant == 2) return f(Cfg<3, R, 4, 8, 32>{});
+        return f(Cfg<3, R, 4, 16, 16>{});
     }
 }
 
@@ -542,17 +542,34 @@ int64_t plan_t(StepArgs& a, int xchunk)
     return a.stencil_blocks + nsb;
 }
 
+// Index of padded element j ([rows][nzp]) in the unpadded caller array
+// ([rows][nz]), or -1 for a padding column.
+__device__ __forceinline__ int64_t unpadded(int64_t j, int64_t nz, int64_t nzp)
+{
+    if (nz == nzp) return j;
+    const int64_t row = j / nzp, z = j - row * nzp;
+    return z < nz ? row * nz + z : -1;
+}
+
 __global__ __launch_bounds__(kBlock) void k_check_fields(const float* __restrict__ m,
                                                          const float* __restrict__ eta,
-                                                         int64_t n, float* __restrict__ partial,
+                                                         int64_t rows, int64_t nz, int64_t nzp,
+                                                         float* __restrict__ partial,
                                                          float* __restrict__ alpha,
                                                          float* __restrict__ beta, float dt)
 {
     __shared__ float smin_m[kBlock], smin_e[kBlock], sbad[kBlock];
     float mn = INFINITY, en = INFINITY, bad = 0.f;
     const float hdt = 0.5f * dt, dt2 = dt * dt;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
+    const int64_t n = rows * nzp;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = unpadded(j, nz, nzp);
+        if (i < 0) {
+            alpha[j] = 0.f;
+            beta[j] = 0.f;
+            continue;
+        }
         const float mm = m[i];
         if (!(mm > 0.f) || !isfinite(mm)) bad += 1.f;
         else mn = fminf(mn, mm);
@@ -564,8 +581,8 @@ __global__ __launch_bounds__(kBlock) void k_check_fields(const float* __restrict
             e *= hdt;
         }
         const float am = mm + e;
-        alpha[i] = dt2 / am;
-        beta[i] = (mm - e) / am;
+        alpha[j] = dt2 / am;
+        beta[j] = (mm - e) / am;
     }
     smin_m[threadIdx.x] = mn;
     smin_e[threadIdx.x] = en;
@@ -596,20 +613,27 @@ __global__ __launch_bounds__(kBlock) void k_fill(float* __restrict__ p, int64_t 
 // Diffusion set-up: per block {max a, count of invalid a} and the step
 // coefficients of forward Euler written in the leapfrog form of the step
 // kernel: alpha = dt a, beta = 0, so out = cur + dt a L cur.
-__global__ __launch_bounds__(kBlock) void k_diffusion_coef(const float* __restrict__ a, int64_t n,
+__global__ __launch_bounds__(kBlock) void k_diffusion_coef(const float* __restrict__ a, int64_t rows,
+                                                           int64_t nz, int64_t nzp,
                                                            float* __restrict__ partial,
                                                            float* __restrict__ alpha,
                                                            float* __restrict__ beta, float dt)
 {
     __shared__ float smax[kBlock], sbad[kBlock];
     float mx = 0.f, bad = 0.f;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
+    const int64_t n = rows * nzp;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = unpadded(j, nz, nzp);
+        beta[j] = 0.f;
+        if (i < 0) {
+            alpha[j] = 0.f;
+            continue;
+        }
         const float v = a[i];
         if (!(v >= 0.f) || !isfinite(v)) bad += 1.f;
         else mx = fmaxf(mx, v);
-        alpha[i] = dt * v;
-        beta[i] = 0.f;
+        alpha[j] = dt * v;
     }
     smax[threadIdx.x] = mx;
     sbad[threadIdx.x] = bad;
@@ -778,10 +802,9 @@ int grid_for(int64_t n)
 
 }  // namespace
 
-int tile_variants(int ndim, int64_t nz)
+int tile_variants(int, int64_t)
 {
-    if (ndim == 2) return 3;
-    return nz % 4 == 0 ? 3 : 1;
+    return 3;
 }
 
 int64_t plan_tiles(int ndim, int order, TileCfg cfg, StepArgs& a)
@@ -854,11 +877,13 @@ hipError_t launch_batch(int ndim, int order, int64_t nz_any, TileCfg cfg, const 
     });
 }
 
-hipError_t launch_check_fields(const float* m, const float* eta, int64_t n, float* partial,
-                               int nblocks, float* alpha, float* beta, float dt, hipStream_t s)
+hipError_t launch_check_fields(const float* m, const float* eta, int64_t rows, int64_t nz,
+                               int64_t nzp, float* partial, int nblocks, float* alpha, float* beta,
+                               float dt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_check_fields, dim3(nblocks), dim3(kBlock), 0, s, m, eta, n, partial,
-                       alpha, beta, dt);
+    if (nzp < nz || nzp % 4 != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_check_fields, dim3(nblocks), dim3(kBlock), 0, s, m, eta, rows, nz, nzp,
+                       partial, alpha, beta, dt);
     return hipGetLastError();
 }
 
@@ -904,11 +929,13 @@ hipError_t launch_ckpt_decode(const unsigned short* in_u, const unsigned short* 
     return hipGetLastError();
 }
 
-hipError_t launch_diffusion_coef(const float* a, int64_t n, float* partial, int nblocks,
-                                 float* alpha, float* beta, float dt, hipStream_t s)
+hipError_t launch_diffusion_coef(const float* a, int64_t rows, int64_t nz, int64_t nzp,
+                                 float* partial, int nblocks, float* alpha, float* beta, float dt,
+                                 hipStream_t s)
 {
-    hipLaunchKernelGGL(k_diffusion_coef, dim3(nblocks), dim3(kBlock), 0, s, a, n, partial, alpha,
-                       beta, dt);
+    if (nzp < nz || nzp % 4 != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_diffusion_coef, dim3(nblocks), dim3(kBlock), 0, s, a, rows, nz, nzp,
+                       partial, alpha, beta, dt);
     return hipGetLastError();
 }
 

@@ -103,6 +103,14 @@ __device__ __forceinline__ void lds_barrier()
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// smallest divisor of s that is at least want (s itself if none is smaller)
+constexpr int pre_ring(int s, int want)
+{
+    for (int r = want; r < s; ++r)
+        if (s % r == 0) return r;
+    return s;
+}
+
 template <int DIM, int R, int VZ, int TZL, int TY>
 struct Tile {
     static constexpr int NT = TZL * TY;
@@ -114,6 +122,13 @@ struct Tile {
     static constexpr int NHZ = TY * 2 * (RZ / VZ);          // z-halo vectors per plane
     static constexpr int KH = (NHY + NHZ + NT - 1) / NT;    // halo vectors per thread
     static constexpr int S = 2 * R + 2;                     // queue slots
+    // Per-plane operands (previous level, alpha, beta) come from a ring of PR
+    // slots, fetched PR-1 planes ahead.  In 2D a plane is one row of the
+    // tile, too little work to cover a load issued one plane earlier, so the
+    // ring is deeper there (measured: 2.5 % on the batched 2D shots).  PR
+    // divides S so that the unrolled group of S planes addresses every slot
+    // at a compile-time index.
+    static constexpr int PR = DIM == 2 ? pre_ring(S, 4) : 2;
     // Halo lead: in 3D, the y/z halo of plane p is loaded together with the
     // queue load of p (R+1 planes before its use) and held in registers, so it
     // is read while the neighbouring tile's load of the same rows is still in
@@ -129,6 +144,7 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
 {
     using T = Tile<DIM, R, VZ, TZL, TY>;
     constexpr int NT = T::NT, TZ = T::TZ, RZ = T::RZ, PITCH = T::PITCH, S = T::S, KH = T::KH;
+    constexpr int PR = T::PR;
     __shared__ __attribute__((aligned(16))) float lds[2][T::ROWS * PITCH];
 
     const int64_t nx = a.nx, ny = a.ny, nz = a.nz;
@@ -194,12 +210,12 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
     for (int k = 0; k < 2 * R + 1; ++k) Q[k] = center(x0 + dir * (k - R));
     Q[S - 1] = vzero<VZ>();
 
-    // per-plane operands, double-buffered so plane x+1 is in flight while x is computed
+    // per-plane operands, fetched PR-1 planes ahead of their use
     struct Pre {
         Vec<VZ> halo[KH];
         Vec<VZ> uo, al, be;
     };
-    Pre pre0, pre1;
+    Pre pre[PR];
     // halo ring of the lead mode (one slot per plane of lead)
     constexpr int HS = T::LEAD ? R + 1 : 1;
     Vec<VZ> hring[HS][KH];
@@ -223,7 +239,9 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
             P.be = vload_once<VZ, T::HINT>(a.beta + xx * sx + col);
         }
     };
-    if (count > 0) fetch(pre0, x0);
+#pragma unroll
+    for (int k = 0; k < PR - 1; ++k)
+        if (k < count) fetch(pre[k], x0 + dir * k);
     if (T::LEAD) {
 #pragma unroll
         for (int k = 0; k < HS; ++k) load_halo(hring[k], k < count ? x0 + dir * k : -1);
@@ -239,8 +257,8 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
         constexpr int U = decltype(UC)::value;
         constexpr int B = U & 1;
         const int64_t x = x0 + dir * i;
-        Pre& P = B ? pre1 : pre0;
-        if (i + 1 < count) fetch(B ? pre0 : pre1, x + dir);
+        Pre& P = pre[U % PR];
+        if (i + PR - 1 < count) fetch(pre[(U + PR - 1) % PR], x + dir * (PR - 1));
         Q[(U + 2 * R + 1) % S] = center(x + dir * (R + 1));
         float* Ls = lds[B];
         const Vec<VZ> c = Q[(U + R) % S];

@@ -389,12 +389,17 @@ std::string tune_key(const Geo& G)
     return b;
 }
 
-TileCfg cached_tile(const std::string& key)
+// The tuned tile for `key`, else the default block shape for G with the
+// x-chunk chosen by the planner.
+TileCfg cached_tile(const std::string& key, const Geo& G)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_locked();
     auto it = g_tune.find(key);
-    return it == g_tune.end() ? TileCfg{} : tile_from_id(it->second);
+    if (it != g_tune.end()) return tile_from_id(it->second);
+    TileCfg c;
+    c.variant = default_variant(G.ndim, G.n[1], G.nzp);
+    return c;
 }
 
 void store_tile(const std::string& key, int id)
@@ -492,7 +497,7 @@ int setup(Ctx& C, int op, const wave_grid* grid, const float* m, const float* et
     if ((rc = check_ws(C.P, o))) return rc;
     C.ws = static_cast<char*>(o->workspace);
     C.s = static_cast<hipStream_t>(stream);
-    C.cfg = o->tile > 0 ? tile_from_id(o->tile) : cached_tile(tune_key(C.G));
+    C.cfg = o->tile > 0 ? tile_from_id(o->tile) : cached_tile(tune_key(C.G), C.G);
     set_weights(C);
     const bool fwd = op != WAVE_OP_ADJOINT, adj = op != WAVE_OP_FORWARD;
     if (fwd) make_inject(C.G, C.src, &C.inj_src);
@@ -1252,7 +1257,8 @@ int wave_forward_batch(int32_t nshots, const wave_shot* shots, const wave_opts* 
         char* ws = static_cast<char*>(opts->workspace);
         hipStream_t st = static_cast<hipStream_t>(stream);
         if ((rc = batch_setup(B, shots, ws, st))) return rc;
-        const TileCfg cfg = opts->tile > 0 ? tile_from_id(opts->tile) : cached_tile(batch_key(B));
+        const TileCfg cfg = opts->tile > 0 ? tile_from_id(opts->tile)
+                                           : cached_tile(batch_key(B), B.shots[0].G);
         std::vector<ShotDesc> desc;
         std::vector<int64_t> begin;
         int64_t blocks = 0;
@@ -1399,7 +1405,7 @@ int wave_diffusion(const wave_grid* grid, const float* a, const float* u0, float
         if ((rc = check_ws(C.P, opts))) return rc;
         C.ws = static_cast<char*>(opts->workspace);
         C.s = static_cast<hipStream_t>(stream);
-        C.cfg = opts->tile > 0 ? tile_from_id(opts->tile) : cached_tile(tune_key(C.G));
+        C.cfg = opts->tile > 0 ? tile_from_id(opts->tile) : cached_tile(tune_key(C.G), C.G);
         set_weights(C);
         const int64_t N = C.G.npad();
         char* host = nullptr;

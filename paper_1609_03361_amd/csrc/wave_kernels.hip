@@ -504,7 +504,8 @@ struct Cfg {
 // fields), so every row starts 16-byte aligned.  2D: one wave with four
 // z-points per lane (256 z), 128 scalar lanes (128 z) or one wave with two
 // z-points per lane (128 z); 3D (four z-points per lane): 64 z x 16 rows,
-// 64 z x 8 rows or 32 z x 32 rows.
+// 64 z x 8 rows, 32 z x 32 rows, 100 z x 10 rows or 200 z x 5 rows.  The
+// last two cover grids such as 200^3 without a mostly empty last tile.
 template <int DIM, int R, class F>
 hipError_t with_shape(int variant, int64_t nz, F&& f)
 {
@@ -516,6 +517,8 @@ hipError_t with_shape(int variant, int64_t nz, F&& f)
     } else {
         if (variant == 1) return f(Cfg<3, R, 4, 16, 8>{});
         if (variant == 2) return f(Cfg<3, R, 4, 8, 32>{});
+        if (variant == 3) return f(Cfg<3, R, 4, 25, 10>{});
+        if (variant == 4) return f(Cfg<3, R, 4, 50, 5>{});
         return f(Cfg<3, R, 4, 16, 16>{});
     }
 }
@@ -541,12 +544,14 @@ int64_t plan_t(StepArgs& a, int xchunk)
     a.nty = C::DIM == 3 ? (int32_t)((a.ny + C::TY - 1) / C::TY) : 1;
     const int64_t tiles = (int64_t)a.ntz * a.nty;
     if (xchunk <= 0) {
-        // about eight blocks per CU on 256 CUs, so that enough loads are in
-        // flight, but no chunk shorter than 2R planes (3D: 16), which would
+        // enough blocks to fill 256 CUs several times over (3D up to order
+        // 12: about 1024, every block resident at once; otherwise about 2048),
+        // but no chunk shorter than 2R planes (3D: at least 8), which would
         // spend most of the block on its 2R-plane prologue
-        const int64_t want_chunks = (2048 + tiles - 1) / tiles;
+        constexpr int64_t want = (C::DIM == 3 && C::R <= 6) ? 1024 : 2048;
+        const int64_t want_chunks = (want + tiles - 1) / tiles;
         int64_t xc = (a.nx + want_chunks - 1) / want_chunks;
-        const int64_t xmin = C::DIM == 3 ? (2 * C::R > 16 ? 2 * C::R : 16) : 2 * C::R;
+        const int64_t xmin = C::DIM == 3 ? (2 * C::R > 8 ? 2 * C::R : 8) : 2 * C::R;
         if (xc < xmin) xc = xmin;
         xchunk = (int)(xc < a.nx ? xc : a.nx);
     }
@@ -820,9 +825,29 @@ int grid_for(int64_t n)
 
 }  // namespace
 
-int tile_variants(int, int64_t)
+int tile_variants(int ndim, int64_t)
 {
-    return 3;
+    return ndim == 2 ? 3 : 5;
+}
+
+int default_variant(int ndim, int64_t ny, int64_t nz)
+{
+    if (ndim == 2) return 0;      // one wave of float4 lanes measured fastest in 2D
+    int best = 0;
+    double best_eff = -1.0;
+    for (int v = 0; v < tile_variants(3, nz); ++v) {
+        double eff = 0.0;
+        (void)with_shape<3, 1>(v, nz, [&](auto C) {
+            using T = typename decltype(C)::T;
+            const double fz = (double)nz / (double)(((nz + T::TZ - 1) / T::TZ) * T::TZ);
+            const double fy = (double)ny / (double)(((ny + C.TY - 1) / C.TY) * C.TY);
+            const double fw = (double)T::NT / (double)(((T::NT + 63) / 64) * 64);
+            eff = fz * fy * fw;
+            return hipSuccess;
+        });
+        if (eff > best_eff + 1e-9) { best_eff = eff; best = v; }
+    }
+    return best;
 }
 
 int64_t plan_tiles(int ndim, int order, TileCfg cfg, StepArgs& a)

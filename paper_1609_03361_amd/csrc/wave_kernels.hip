@@ -11,6 +11,7 @@
 // Blocks past `stencil_blocks` sample `cur` at the sparse points (Section
 // "Sparse point interpolation"): `cur` is read-only during the step, so the
 // sampling needs no ordering with the update.
+#include <atomic>
 #include "wave_internal.h"
 
 #include <hip/hip_fp16.h>
@@ -214,6 +215,7 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
     struct Pre {
         Vec<VZ> halo[KH];
         Vec<VZ> uo, al, be;
+        Vec<VZ> fw, gr;          // imaging: forward wavefield u^k and gradient
     };
     Pre pre[PR];
     // halo ring of the lead mode (one slot per plane of lead)
@@ -237,6 +239,10 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
             P.uo = vload_once<VZ, T::HINT>(a.other + xx * sx + col);
             P.al = vload_once<VZ, T::HINT>(a.alpha + xx * sx + col);
             P.be = vload_once<VZ, T::HINT>(a.beta + xx * sx + col);
+            if constexpr (IMG) {
+                P.fw = vload_once<VZ, T::HINT>(a.img_fwd + xx * sx + col);
+                P.gr = vload_once<VZ, T::HINT>(a.img_grad + xx * sx + col);
+            }
         }
     };
 #pragma unroll
@@ -352,15 +358,14 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
         }
         if (own) {
             const int64_t off = x * sx + col;
-            if (IMG) {
-                const Vec<VZ> f = vload<VZ>(a.img_fwd + off);
-                Vec<VZ> g = vload<VZ>(a.img_grad + off);
+            if constexpr (IMG) {
+                Vec<VZ> g = P.gr;
 #pragma unroll
                 for (int v = 0; v < VZ; ++v) {
                     const float d2 = (P.uo[v] + o[v]) + m2c[v];
-                    g[v] = fmaf(-f[v] * a.inv_dt2, d2, g[v]);
+                    g[v] = fmaf(-P.fw[v] * a.inv_dt2, d2, g[v]);
                 }
-                vstore<VZ>(a.img_grad + off, g);
+                vstore_once<VZ, T::HINT>(a.img_grad + off, g);
             }
             vstore_once<VZ, T::HINT>(a.out + off, o);
         }
@@ -537,20 +542,28 @@ hipError_t with_cfg(int ndim, int order, int variant, int64_t nz, F&& f)
 }
 
 template <class C>
-int64_t plan_t(StepArgs& a, int xchunk)
+int64_t plan_t(StepArgs& a, int xchunk, int64_t resident = 0)
 {
     using T = typename C::T;
     a.ntz = (int32_t)((a.nz + T::TZ - 1) / T::TZ);
     a.nty = C::DIM == 3 ? (int32_t)((a.ny + C::TY - 1) / C::TY) : 1;
     const int64_t tiles = (int64_t)a.ntz * a.nty;
     if (xchunk <= 0) {
-        // enough blocks to fill 256 CUs several times over (3D up to order
-        // 12: about 1024, every block resident at once; otherwise about 2048),
-        // but no chunk shorter than 2R planes (3D: at least 8), which would
-        // spend most of the block on its 2R-plane prologue
-        constexpr int64_t want = (C::DIM == 3 && C::R <= 6) ? 1024 : 2048;
-        const int64_t want_chunks = (want + tiles - 1) / tiles;
-        int64_t xc = (a.nx + want_chunks - 1) / want_chunks;
+        // 3D up to order 12: as many blocks as the chip holds at once
+        // (`resident`, from the kernel's occupancy; about 1024 when unknown),
+        // so that no second, partly empty round of blocks follows; otherwise
+        // about 2048 blocks.  No chunk is shorter than 2R planes (3D: at
+        // least 8), which would spend most of the block on its prologue.
+        int64_t xc;
+        if (C::DIM == 3 && C::R <= 6) {
+            const int64_t want = resident > 0 ? resident : 1024;
+            int64_t chunks = want / tiles;
+            if (chunks < 1) chunks = 1;
+            xc = (a.nx + chunks - 1) / chunks;
+        } else {
+            const int64_t want_chunks = (2048 + tiles - 1) / tiles;
+            xc = (a.nx + want_chunks - 1) / want_chunks;
+        }
         const int64_t xmin = C::DIM == 3 ? (2 * C::R > 8 ? 2 * C::R : 8) : 2 * C::R;
         if (xc < xmin) xc = xmin;
         xchunk = (int)(xc < a.nx ? xc : a.nx);
@@ -860,20 +873,40 @@ int64_t plan_tiles(int ndim, int order, TileCfg cfg, StepArgs& a)
     return blocks;
 }
 
+// Blocks of `kern` (nt threads each) resident on the whole device at once;
+// 0 if the runtime cannot say.  Cached per kernel (one device type).
+template <class K>
+int64_t resident_blocks(K kern, int nt, std::atomic<int64_t>& cache)
+{
+    int64_t r = cache.load(std::memory_order_relaxed);
+    if (r >= 0) return r;
+    int dev = 0, cus = 0, per_cu = 0;
+    r = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), nt,
+                                                     0) == hipSuccess)
+        r = (int64_t)per_cu * cus;
+    cache.store(r, std::memory_order_relaxed);
+    return r;
+}
+
 hipError_t launch_step(int ndim, int order, const StepArgs& a0, hipStream_t s, TileCfg cfg)
 {
     return with_cfg(ndim, order, cfg.variant, a0.nz, [&](auto C) {
         using CC = decltype(C);
-        StepArgs a = a0;
-        const int64_t blocks = plan_t<CC>(a, cfg.xchunk);
-        if (!(a.smp_out && a.smp.npts > 0)) a.smp.npts = 0;
-        if (a.img_grad)
-            hipLaunchKernelGGL((k_step_stream<CC::DIM, CC::R, CC::VZ, CC::TZL, CC::TY, true>),
-                               dim3((unsigned)blocks), dim3(CC::T::NT), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_step_stream<CC::DIM, CC::R, CC::VZ, CC::TZL, CC::TY, false>),
-                               dim3((unsigned)blocks), dim3(CC::T::NT), 0, s, a);
-        return hipGetLastError();
+        auto launch = [&](auto kern, std::atomic<int64_t>& cache) {
+            StepArgs a = a0;
+            const int64_t res = cfg.xchunk <= 0 ? resident_blocks(kern, CC::T::NT, cache) : 0;
+            const int64_t blocks = plan_t<CC>(a, cfg.xchunk, res);
+            if (!(a.smp_out && a.smp.npts > 0)) a.smp.npts = 0;
+            hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(CC::T::NT), 0, s, a);
+            return hipGetLastError();
+        };
+        static std::atomic<int64_t> res_img{-1}, res_plain{-1};
+        if (a0.img_grad)
+            return launch(k_step_stream<CC::DIM, CC::R, CC::VZ, CC::TZL, CC::TY, true>, res_img);
+        return launch(k_step_stream<CC::DIM, CC::R, CC::VZ, CC::TZL, CC::TY, false>, res_plain);
     });
 }
 

@@ -72,6 +72,7 @@ int prof_end(hipStream_t s)
 
 constexpr size_t kAlign = 256;
 constexpr int kCheckBlocks = 2048;
+constexpr int kRedFloats = 1024;   // reduction scratch: misfit partials, checkpoint maxima
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -351,7 +352,7 @@ Plan make_plan(int op, const Geo& G, int nsrc, int nrec, const wave_opts* o)
         P.gacc = c.take(N * 4);
         P.resid = c.take((size_t)G.nt * nrec * 4);
         P.dsyn = c.take((size_t)G.nt * nrec * 4);
-        P.red = c.take(1024 * 4);
+        P.red = c.take(kRedFloats * 4);
         P.ckpt = c.take(ckpt_bytes(G, o));
     }
     P.total = c.off;
@@ -621,6 +622,7 @@ int store_checkpoint(const Ctx& C, const CkptView& v, int c, const float* cur, c
         return WAVE_OK;
     }
     HIP_TRY(launch_ckpt_encode(cur, prev, N, v.dtype == WAVE_CKPT_BF16, v.slot(c),
+                               C.at<float>(C.P.red), kRedFloats / 2,
                                static_cast<unsigned short*>(v.snapshot(c, 0)),
                                static_cast<unsigned short*>(v.snapshot(c, 1)), C.s));
     return WAVE_OK;
@@ -1215,7 +1217,7 @@ int wave_gradient(const wave_grid* grid, const float* m, const float* eta, const
         if (rc) return rc;
         const int64_t nd = (int64_t)C.G.nt * C.rec.npts;
         float* resid = C.at<float>(C.P.resid);
-        HIP_TRY(launch_residual(dsyn, d_obs, resid, nd, C.at<float>(C.P.red), 1024, misfit, C.s));
+        HIP_TRY(launch_residual(dsyn, d_obs, resid, nd, C.at<float>(C.P.red), kRedFloats, misfit, C.s));
         return run_backward(C, q, resid, ck, grad, nullptr, false);
     } catch (const std::exception& e) {
         return fail(WAVE_EINVAL, "exception: %s", e.what());

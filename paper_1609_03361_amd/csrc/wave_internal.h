@@ -122,10 +122,13 @@ hipError_t launch_diffusion_coef(const float* a, int64_t rows, int64_t nz, int64
                                  hipStream_t s);
 // Reduced-precision checkpoint of (cur, prev): stores cur and cur - prev as
 // BF16 (bf16 != 0) or FP16 with per-array power-of-two scales kept in `slot`
-// (4 words: scale_u, scale_d, and two reduction words).
+// (4 words: scale_u, scale_d, max|u| and max|d| bits).  The maxima go
+// through `partial` (2 * nblocks floats of scratch, at most nblocks blocks)
+// and a one-block pass, without atomics.  n is a multiple of 4 (fields use
+// padded rows); four values per thread, 8-byte stores.
 hipError_t launch_ckpt_encode(const float* cur, const float* prev, int64_t n, int bf16,
-                              unsigned int* slot, unsigned short* out_u, unsigned short* out_d,
-                              hipStream_t s);
+                              unsigned int* slot, float* partial, int nblocks,
+                              unsigned short* out_u, unsigned short* out_d, hipStream_t s);
 hipError_t launch_ckpt_decode(const unsigned short* in_u, const unsigned short* in_d,
                               const unsigned int* slot, int64_t n, int bf16, float* cur, float* prev,
                               hipStream_t s);

@@ -11,6 +11,7 @@
 // Blocks past `stencil_blocks` sample `cur` at the sparse points (Section
 // "Sparse point interpolation"): `cur` is read-only during the step, so the
 // sampling needs no ordering with the update.
+#include <algorithm>
 #include <atomic>
 #include "wave_internal.h"
 
@@ -756,17 +757,22 @@ __device__ __forceinline__ float scale_for(unsigned int maxbits)
     return ldexpf(1.f, e);
 }
 
+// Per block {max |u|, max |u - prev|} into partial[2b], partial[2b+1].
 __global__ __launch_bounds__(kBlock) void k_ckpt_max(const float* __restrict__ cur,
                                                      const float* __restrict__ prev, int64_t n,
-                                                     unsigned int* __restrict__ slot)
+                                                     float* __restrict__ partial)
 {
     __shared__ float sa[kBlock], sd[kBlock];
     float ma = 0.f, md = 0.f;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+    const int64_t n4 = n / 4;      // n is a multiple of 4 (padded rows)
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n4;
          i += (int64_t)gridDim.x * kBlock) {
-        const float c = cur[i];
-        ma = fmaxf(ma, fabsf(c));
-        md = fmaxf(md, fabsf(c - prev[i]));
+        const Vec<4> c = vload<4>(cur + 4 * i), p = vload<4>(prev + 4 * i);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            ma = fmaxf(ma, fabsf(c[v]));
+            md = fmaxf(md, fabsf(c[v] - p[v]));
+        }
     }
     sa[threadIdx.x] = ma;
     sd[threadIdx.x] = md;
@@ -779,34 +785,69 @@ __global__ __launch_bounds__(kBlock) void k_ckpt_max(const float* __restrict__ c
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        atomicMax(slot + 2, __float_as_uint(sa[0]));
-        atomicMax(slot + 3, __float_as_uint(sd[0]));
+        partial[2 * blockIdx.x] = sa[0];
+        partial[2 * blockIdx.x + 1] = sd[0];
+    }
+}
+
+// One block: the maxima over the per-block partials, and the two scales,
+// into the checkpoint's slot (no atomics, so the order never matters).
+__global__ __launch_bounds__(kBlock) void k_ckpt_scale(const float* __restrict__ partial, int nb,
+                                                       unsigned int* __restrict__ slot)
+{
+    __shared__ float sa[kBlock], sd[kBlock];
+    float ma = 0.f, md = 0.f;
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+        ma = fmaxf(ma, partial[2 * b]);
+        md = fmaxf(md, partial[2 * b + 1]);
+    }
+    sa[threadIdx.x] = ma;
+    sd[threadIdx.x] = md;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sa[threadIdx.x] = fmaxf(sa[threadIdx.x], sa[threadIdx.x + w]);
+            sd[threadIdx.x] = fmaxf(sd[threadIdx.x], sd[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const unsigned int bu = __float_as_uint(sa[0]), bd = __float_as_uint(sd[0]);
+        reinterpret_cast<float*>(slot)[0] = scale_for(bu);
+        reinterpret_cast<float*>(slot)[1] = scale_for(bd);
+        slot[2] = bu;
+        slot[3] = bd;
     }
 }
 
 template <bool BF16>
 __global__ __launch_bounds__(kBlock) void k_ckpt_encode(const float* __restrict__ cur,
                                                         const float* __restrict__ prev, int64_t n,
-                                                        unsigned int* __restrict__ slot,
+                                                        const unsigned int* __restrict__ slot,
                                                         unsigned short* __restrict__ out_u,
                                                         unsigned short* __restrict__ out_d)
 {
-    const float su = scale_for(slot[2]), sd = scale_for(slot[3]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        reinterpret_cast<float*>(slot)[0] = su;
-        reinterpret_cast<float*>(slot)[1] = sd;
-    }
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+    const float su = reinterpret_cast<const float*>(slot)[0];
+    const float sd = reinterpret_cast<const float*>(slot)[1];
+    using U4 = unsigned short __attribute__((ext_vector_type(4)));
+    const int64_t n4 = n / 4;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n4;
          i += (int64_t)gridDim.x * kBlock) {
-        const float c = cur[i];
-        const float d = c - prev[i];
-        if (BF16) {
-            out_u[i] = f32_to_bf16_rn(c * su);
-            out_d[i] = f32_to_bf16_rn(d * sd);
-        } else {
-            out_u[i] = __half_as_ushort(__float2half_rn(c * su));
-            out_d[i] = __half_as_ushort(__float2half_rn(d * sd));
+        const Vec<4> c = vload<4>(cur + 4 * i), p = vload<4>(prev + 4 * i);
+        U4 eu, ed;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float d = c[v] - p[v];
+            if (BF16) {
+                eu[v] = f32_to_bf16_rn(c[v] * su);
+                ed[v] = f32_to_bf16_rn(d * sd);
+            } else {
+                eu[v] = __half_as_ushort(__float2half_rn(c[v] * su));
+                ed[v] = __half_as_ushort(__float2half_rn(d * sd));
+            }
         }
+        *reinterpret_cast<U4*>(out_u + 4 * i) = eu;
+        *reinterpret_cast<U4*>(out_d + 4 * i) = ed;
     }
 }
 
@@ -818,13 +859,22 @@ __global__ __launch_bounds__(kBlock) void k_ckpt_decode(const unsigned short* __
                                                         float* __restrict__ prev)
 {
     const float iu = 1.f / slot[0], id = 1.f / slot[1];   // exact: powers of two
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+    using U4 = unsigned short __attribute__((ext_vector_type(4)));
+    const int64_t n4 = n / 4;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n4;
          i += (int64_t)gridDim.x * kBlock) {
-        const float u = BF16 ? bf16_to_f32(in_u[i]) : __half2float(__ushort_as_half(in_u[i]));
-        const float d = BF16 ? bf16_to_f32(in_d[i]) : __half2float(__ushort_as_half(in_d[i]));
-        const float c = u * iu;
-        cur[i] = c;
-        prev[i] = c - d * id;
+        const U4 eu = *reinterpret_cast<const U4*>(in_u + 4 * i);
+        const U4 ed = *reinterpret_cast<const U4*>(in_d + 4 * i);
+        Vec<4> c, p;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float u = BF16 ? bf16_to_f32(eu[v]) : __half2float(__ushort_as_half(eu[v]));
+            const float d = BF16 ? bf16_to_f32(ed[v]) : __half2float(__ushort_as_half(ed[v]));
+            c[v] = u * iu;
+            p[v] = c[v] - d * id;
+        }
+        vstore<4>(cur + 4 * i, c);
+        vstore<4>(prev + 4 * i, p);
     }
 }
 
@@ -974,19 +1024,21 @@ hipError_t launch_residual(const float* d, const float* dobs, float* r, int64_t 
 }
 
 hipError_t launch_ckpt_encode(const float* cur, const float* prev, int64_t n, int bf16,
-                              unsigned int* slot, unsigned short* out_u, unsigned short* out_d,
-                              hipStream_t s)
+                              unsigned int* slot, float* partial, int nblocks,
+                              unsigned short* out_u, unsigned short* out_d, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, s, reinterpret_cast<float*>(slot), 4, 0.f);
+    if (n % 4 != 0 || nblocks < 1) return hipErrorInvalidValue;
+    const int nb = std::min(nblocks, grid_for(n / 4));
+    hipLaunchKernelGGL(k_ckpt_max, dim3(nb), dim3(kBlock), 0, s, cur, prev, n, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ckpt_max, dim3(grid_for(n)), dim3(kBlock), 0, s, cur, prev, n, slot);
+    hipLaunchKernelGGL(k_ckpt_scale, dim3(1), dim3(kBlock), 0, s, partial, nb, slot);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (bf16)
-        hipLaunchKernelGGL(k_ckpt_encode<true>, dim3(grid_for(n)), dim3(kBlock), 0, s, cur, prev, n,
-                           slot, out_u, out_d);
+        hipLaunchKernelGGL(k_ckpt_encode<true>, dim3(grid_for(n / 4)), dim3(kBlock), 0, s, cur, prev,
+                           n, slot, out_u, out_d);
     else
-        hipLaunchKernelGGL(k_ckpt_encode<false>, dim3(grid_for(n)), dim3(kBlock), 0, s, cur, prev,
+        hipLaunchKernelGGL(k_ckpt_encode<false>, dim3(grid_for(n / 4)), dim3(kBlock), 0, s, cur, prev,
                            n, slot, out_u, out_d);
     return hipGetLastError();
 }
@@ -995,13 +1047,14 @@ hipError_t launch_ckpt_decode(const unsigned short* in_u, const unsigned short* 
                               const unsigned int* slot, int64_t n, int bf16, float* cur, float* prev,
                               hipStream_t s)
 {
+    if (n % 4 != 0) return hipErrorInvalidValue;
     const float* sl = reinterpret_cast<const float*>(slot);
     if (bf16)
-        hipLaunchKernelGGL(k_ckpt_decode<true>, dim3(grid_for(n)), dim3(kBlock), 0, s, in_u, in_d,
-                           sl, n, cur, prev);
+        hipLaunchKernelGGL(k_ckpt_decode<true>, dim3(grid_for(n / 4)), dim3(kBlock), 0, s, in_u,
+                           in_d, sl, n, cur, prev);
     else
-        hipLaunchKernelGGL(k_ckpt_decode<false>, dim3(grid_for(n)), dim3(kBlock), 0, s, in_u, in_d,
-                           sl, n, cur, prev);
+        hipLaunchKernelGGL(k_ckpt_decode<false>, dim3(grid_for(n / 4)), dim3(kBlock), 0, s, in_u,
+                           in_d, sl, n, cur, prev);
     return hipGetLastError();
 }
 

@@ -399,7 +399,7 @@ TileCfg cached_tile(const std::string& key, const Geo& G)
     auto it = g_tune.find(key);
     if (it != g_tune.end()) return tile_from_id(it->second);
     TileCfg c;
-    c.variant = default_variant(G.ndim, G.n[1], G.nzp);
+    c.variant = default_variant(G.ndim, G.order, G.n[1], G.nzp);
     return c;
 }
 

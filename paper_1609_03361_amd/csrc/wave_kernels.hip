@@ -509,9 +509,10 @@ struct Cfg {
 // Block shapes.  The row length nz is a multiple of 4 (the library pads its
 // fields), so every row starts 16-byte aligned.  2D: one wave with four
 // z-points per lane (256 z), 128 scalar lanes (128 z) or one wave with two
-// z-points per lane (128 z); 3D (four z-points per lane): 64 z x 16 rows,
-// 64 z x 8 rows, 32 z x 32 rows, 100 z x 10 rows or 200 z x 5 rows.  The
-// last two cover grids such as 200^3 without a mostly empty last tile.
+// z-points per lane (128 z); 3D, four z-points per lane: 64 z x 16 rows,
+// 64 z x 8 rows, 32 z x 32 rows, 100 z x 10 rows or 200 z x 5 rows (the
+// last two cover grids such as 200^3 without a mostly empty last tile); 3D,
+// two z-points per lane: 64 z x 8 rows (half the queue registers per lane).
 template <int DIM, int R, class F>
 hipError_t with_shape(int variant, int64_t nz, F&& f)
 {
@@ -525,6 +526,7 @@ hipError_t with_shape(int variant, int64_t nz, F&& f)
         if (variant == 2) return f(Cfg<3, R, 4, 8, 32>{});
         if (variant == 3) return f(Cfg<3, R, 4, 25, 10>{});
         if (variant == 4) return f(Cfg<3, R, 4, 50, 5>{});
+        if (variant == 5) return f(Cfg<3, R, 2, 32, 8>{});
         return f(Cfg<3, R, 4, 16, 16>{});
     }
 }
@@ -559,7 +561,11 @@ int64_t plan_t(StepArgs& a, int xchunk, int64_t resident = 0)
         // its prologue.
         int64_t xc;
         if (C::DIM == 3) {
-            const int64_t want = resident > 0 ? resident : (C::R <= 6 ? 1024 : 2048);
+            int64_t want = resident > 0 ? resident : (C::R <= 6 ? 1024 : 2048);
+            // two-point lanes: a block is half the work of a four-point one
+            // at the same rows; two rounds of them measured fastest (256^3
+            // order 8: 52.2 us at 16-plane chunks against 53.5 us at 32)
+            if (C::VZ == 2) want *= 2;
             int64_t chunks = want / tiles;
             if (chunks < 1) chunks = 1;
             xc = (a.nx + chunks - 1) / chunks;
@@ -892,15 +898,23 @@ int grid_for(int64_t n)
 
 int tile_variants(int ndim, int64_t)
 {
-    return ndim == 2 ? 3 : 5;
+    return ndim == 2 ? 3 : 6;
 }
 
-int default_variant(int ndim, int64_t ny, int64_t nz)
+int default_variant(int ndim, int order, int64_t ny, int64_t nz)
 {
     if (ndim == 2) return 0;      // one wave of float4 lanes measured fastest in 2D
+    // Candidates in order of preference at equal lane waste: up to order 8
+    // the two-point-lane tile first (256^3 order 8: 52.2 us against 53.8 us
+    // for 64 z x 16 rows of four-point lanes); above, it is slower (512^3
+    // order 16: 596 us against 561 us).
+    const int pref[] = {5, 0, 1, 2, 3, 4};
+    const int base[] = {0, 1, 2, 3, 4, 5};
+    const int* order_of = order <= 8 ? pref : base;
     int best = 0;
     double best_eff = -1.0;
-    for (int v = 0; v < tile_variants(3, nz); ++v) {
+    for (int k = 0; k < tile_variants(3, nz); ++k) {
+        const int v = order_of[k];
         double eff = 0.0;
         (void)with_shape<3, 1>(v, nz, [&](auto C) {
             using T = typename decltype(C)::T;

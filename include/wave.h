@@ -86,7 +86,13 @@ typedef struct {
     int32_t ckpt_every;       /* gradient/checkpointing: steps per segment, 0 = 20 */
     int32_t ckpt_dtype;       /* wave_ckpt_dtype for stored snapshots */
     int32_t tile;             /* 0 = tuned if wave_tune has seen this grid, else automatic;
-                                 > 0 = explicit tile id (variant << 16 | x-chunk planes) */
+                                 > 0 = explicit tile id (variant << 16 | x-chunk planes, 0 =
+                                 planned).  Variants (block shapes, z x rows of the (y, z)
+                                 plane): 2D 0 = 256 z (4 per lane), 1 = 128 z (1 per lane),
+                                 2 = 128 z (2 per lane); 3D 0 = 64 x 16, 1 = 64 x 8,
+                                 2 = 32 x 32, 3 = 100 x 10, 4 = 200 x 5 (4 z-points per
+                                 lane), 5 = 64 x 8 (2 per lane).  An unknown variant or a
+                                 negative id is WAVE_EINVAL.  Results do not depend on it. */
     int32_t flags;            /* WAVE_FLAG_* bits */
 } wave_opts;
 

@@ -403,6 +403,23 @@ TileCfg cached_tile(const std::string& key, const Geo& G)
     return c;
 }
 
+// opts->tile: 0 = cached or default, else an explicit id that must name an
+// existing block shape.
+int pick_tile(const wave_opts* o, const std::string& key, const Geo& G, TileCfg* out)
+{
+    if (o->tile < 0) return fail(WAVE_EINVAL, "tile id %d is negative", o->tile);
+    if (o->tile == 0) {
+        *out = cached_tile(key, G);
+        return WAVE_OK;
+    }
+    const TileCfg c = tile_from_id(o->tile);
+    if (c.variant >= tile_variants(G.ndim, G.nzp))
+        return fail(WAVE_EINVAL, "tile variant %d does not exist (%dD has %d)", c.variant, G.ndim,
+                    tile_variants(G.ndim, G.nzp));
+    *out = c;
+    return WAVE_OK;
+}
+
 void store_tile(const std::string& key, int id)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -498,7 +515,7 @@ int setup(Ctx& C, int op, const wave_grid* grid, const float* m, const float* et
     if ((rc = check_ws(C.P, o))) return rc;
     C.ws = static_cast<char*>(o->workspace);
     C.s = static_cast<hipStream_t>(stream);
-    C.cfg = o->tile > 0 ? tile_from_id(o->tile) : cached_tile(tune_key(C.G), C.G);
+    if ((rc = pick_tile(o, tune_key(C.G), C.G, &C.cfg))) return rc;
     set_weights(C);
     const bool fwd = op != WAVE_OP_ADJOINT, adj = op != WAVE_OP_FORWARD;
     if (fwd) make_inject(C.G, C.src, &C.inj_src);
@@ -1259,8 +1276,8 @@ int wave_forward_batch(int32_t nshots, const wave_shot* shots, const wave_opts* 
         char* ws = static_cast<char*>(opts->workspace);
         hipStream_t st = static_cast<hipStream_t>(stream);
         if ((rc = batch_setup(B, shots, ws, st))) return rc;
-        const TileCfg cfg = opts->tile > 0 ? tile_from_id(opts->tile)
-                                           : cached_tile(batch_key(B), B.shots[0].G);
+        TileCfg cfg;
+        if ((rc = pick_tile(opts, batch_key(B), B.shots[0].G, &cfg))) return rc;
         std::vector<ShotDesc> desc;
         std::vector<int64_t> begin;
         int64_t blocks = 0;
@@ -1407,7 +1424,7 @@ int wave_diffusion(const wave_grid* grid, const float* a, const float* u0, float
         if ((rc = check_ws(C.P, opts))) return rc;
         C.ws = static_cast<char*>(opts->workspace);
         C.s = static_cast<hipStream_t>(stream);
-        C.cfg = opts->tile > 0 ? tile_from_id(opts->tile) : cached_tile(tune_key(C.G), C.G);
+        if ((rc = pick_tile(opts, tune_key(C.G), C.G, &C.cfg))) return rc;
         set_weights(C);
         const int64_t N = C.G.npad();
         char* host = nullptr;

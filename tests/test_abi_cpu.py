@@ -64,13 +64,13 @@ def test_workspace_size_rejects_bad_grids(kw, code):
 
 
 def _forward_rc(shape=(20, 30), src=((50.0, 50.0),), rec=((10.0, 20.0),), ws=True, ws_bytes=None,
-                q=True, d=True, m=True):
+                q=True, d=True, m=True, tile=0):
     nd = len(shape)
     g = L.make_grid(shape, (10.0,) * nd, 4, 1e-3, 5)
     sp = L.HostPoints(src, nd)
     rp = L.HostPoints(rec, nd)
     fake = 1 << 20          # never dereferenced: every case fails validation first
-    o = L.make_opts(fake if ws else 0, ws_bytes if ws_bytes is not None else 1 << 40)
+    o = L.make_opts(fake if ws else 0, ws_bytes if ws_bytes is not None else 1 << 40, tile=tile)
     rc = L.lib().wave_forward(C.byref(g), fake if m else None, None, C.byref(sp.s),
                               fake if q else None, C.byref(rp.s), fake if d else None, None, None,
                               C.byref(o), None)
@@ -95,6 +95,26 @@ def test_forward_argument_errors_return_before_any_device_work():
     assert _forward_rc(ws=False) == L.WAVE_EWORKSPACE
     assert _forward_rc(ws_bytes=1024) == L.WAVE_EWORKSPACE
     assert b"workspace" in L.lib().wave_last_error()
+    # block shapes: 3 in 2D (ids 0..2), 6 in 3D (ids 0..5)
+    assert _forward_rc(tile=(3 << 16) | 8) == L.WAVE_EINVAL
+    assert b"variant 3" in L.lib().wave_last_error()
+    assert _forward_rc(tile=-1) == L.WAVE_EINVAL
+    assert _forward_rc(shape=(20, 30, 40), src=((50.0, 50.0, 50.0),), rec=((10.0, 20.0, 30.0),),
+                       tile=(6 << 16) | 8) == L.WAVE_EINVAL
+
+
+def test_library_fields_use_rows_padded_to_four_points():
+    """Rows inside the workspace and the checkpoints hold nz rounded up to a
+    multiple of 4: nz = 801..804 need the same bytes, nz = 805 more."""
+    sizes = [_size(L.WAVE_OP_GRADIENT, shape=(40, nz))[1] for nz in (801, 802, 803, 804, 805)]
+    assert len(set(sizes[:4])) == 1 and sizes[4] > sizes[3]
+    ck = []
+    for nz in (801, 804, 805):
+        g = L.make_grid((40, nz), (10.0, 10.0), 8, 1e-3, 100)
+        n = C.c_size_t(0)
+        assert L.lib().wave_checkpoint_size(C.byref(g), C.byref(L.make_opts()), C.byref(n)) == 0
+        ck.append(n.value)
+    assert ck[0] == ck[1] < ck[2]
 
 
 def test_checkpoint_size_scales_with_dtype_and_interval():

@@ -552,7 +552,7 @@ int setup(Ctx& C, int op, const wave_grid* grid, const float* m, const float* et
     }
     HIP_TRY(launch_check_fields(m, eta, C.G.nrows(), C.G.n[2], C.G.nzp, C.at<float>(C.P.check),
                                 kCheckBlocks, C.at<float>(C.P.alpha), C.at<float>(C.P.beta),
-                                (float)C.G.dt, C.s));
+                                C.G.dt, C.s));
     HIP_TRY(hipMemcpyAsync(part, C.at<float>(C.P.check), part_bytes, hipMemcpyDeviceToHost, C.s));
     HIP_TRY(hipEventRecord(g_stage.done, C.s));
     HIP_TRY(hipStreamSynchronize(C.s));
@@ -927,7 +927,7 @@ int batch_setup(const BatchPlan& B, const wave_shot* shots, char* ws, hipStream_
         HIP_TRY(launch_check_fields(shots[i].m, shots[i].eta, S.G.nrows(), S.G.n[2], S.G.nzp,
                                     reinterpret_cast<float*>(ws + B.check) + (size_t)i * kCheckBlocksShot * 3,
                                     kCheckBlocksShot, reinterpret_cast<float*>(ws + S.alpha),
-                                    reinterpret_cast<float*>(ws + S.beta), (float)S.G.dt, st));
+                                    reinterpret_cast<float*>(ws + S.beta), S.G.dt, st));
     }
     HIP_TRY(hipMemcpyAsync(part, ws + B.check, part_bytes, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipEventRecord(g_stage.done, st));
@@ -1432,7 +1432,7 @@ int wave_diffusion(const wave_grid* grid, const float* a, const float* u0, float
         float* part = reinterpret_cast<float*>(host);
         HIP_TRY(launch_diffusion_coef(a, C.G.nrows(), C.G.n[2], C.G.nzp, C.at<float>(C.P.check),
                                       kCheckBlocks, C.at<float>(C.P.alpha), C.at<float>(C.P.beta),
-                                      (float)C.G.dt, C.s));
+                                      C.G.dt, C.s));
         HIP_TRY(hipMemcpyAsync(part, C.at<float>(C.P.check), (size_t)kCheckBlocks * 2 * 4,
                                hipMemcpyDeviceToHost, C.s));
         HIP_TRY(hipEventRecord(g_stage.done, C.s));

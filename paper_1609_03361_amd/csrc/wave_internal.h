@@ -114,12 +114,12 @@ hipError_t launch_batch_persistent(int ndim, int order, int64_t nz_any, TileCfg 
 // zeros in the padding columns nz <= z < nzp.
 hipError_t launch_check_fields(const float* m, const float* eta, int64_t rows, int64_t nz,
                                int64_t nzp, float* partial, int nblocks, float* alpha, float* beta,
-                               float dt, hipStream_t s);
+                               double dt, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
 // Diffusion coefficients alpha = dt a, beta = 0 and per block {max a, invalid count}
 // into `partial` (2 * nblocks floats); a is [rows][nz], alpha and beta [rows][nzp].
 hipError_t launch_diffusion_coef(const float* a, int64_t rows, int64_t nz, int64_t nzp,
-                                 float* partial, int nblocks, float* alpha, float* beta, float dt,
+                                 float* partial, int nblocks, float* alpha, float* beta, double dt,
                                  hipStream_t s);
 // Reduced-precision checkpoint of (cur, prev): stores cur and cur - prev as
 // BF16 (bf16 != 0) or FP16 with per-array power-of-two scales kept in `slot`

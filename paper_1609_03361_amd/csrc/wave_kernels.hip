@@ -601,11 +601,15 @@ __global__ __launch_bounds__(kBlock) void k_check_fields(const float* __restrict
                                                          int64_t rows, int64_t nz, int64_t nzp,
                                                          float* __restrict__ partial,
                                                          float* __restrict__ alpha,
-                                                         float* __restrict__ beta, float dt)
+                                                         float* __restrict__ beta, double dt)
 {
+    // The coefficients are formed in FP64 and rounded once to FP32: the same
+    // rounding of dt^2 or of m + eta dt/2 at every point of a layer would act
+    // as a small systematic change of velocity, whose phase error grows with
+    // the number of steps.
     __shared__ float smin_m[kBlock], smin_e[kBlock], sbad[kBlock];
     float mn = INFINITY, en = INFINITY, bad = 0.f;
-    const float hdt = 0.5f * dt, dt2 = dt * dt;
+    const double hdt = 0.5 * dt, dt2 = dt * dt;
     const int64_t n = rows * nzp;
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n;
          j += (int64_t)gridDim.x * kBlock) {
@@ -618,16 +622,16 @@ __global__ __launch_bounds__(kBlock) void k_check_fields(const float* __restrict
         const float mm = m[i];
         if (!(mm > 0.f) || !isfinite(mm)) bad += 1.f;
         else mn = fminf(mn, mm);
-        float e = 0.f;
+        double e = 0.0;
         if (eta) {
-            e = eta[i];
-            if (!(e >= 0.f) || !isfinite(e)) bad += 1.f;
-            else en = fminf(en, e);
-            e *= hdt;
+            const float ef = eta[i];
+            if (!(ef >= 0.f) || !isfinite(ef)) bad += 1.f;
+            else en = fminf(en, ef);
+            e = (double)ef * hdt;
         }
-        const float am = mm + e;
-        alpha[j] = dt2 / am;
-        beta[j] = (mm - e) / am;
+        const double am = (double)mm + e;
+        alpha[j] = (float)(dt2 / am);
+        beta[j] = (float)(((double)mm - e) / am);
     }
     smin_m[threadIdx.x] = mn;
     smin_e[threadIdx.x] = en;
@@ -662,7 +666,7 @@ __global__ __launch_bounds__(kBlock) void k_diffusion_coef(const float* __restri
                                                            int64_t nz, int64_t nzp,
                                                            float* __restrict__ partial,
                                                            float* __restrict__ alpha,
-                                                           float* __restrict__ beta, float dt)
+                                                           float* __restrict__ beta, double dt)
 {
     __shared__ float smax[kBlock], sbad[kBlock];
     float mx = 0.f, bad = 0.f;
@@ -678,7 +682,7 @@ __global__ __launch_bounds__(kBlock) void k_diffusion_coef(const float* __restri
         const float v = a[i];
         if (!(v >= 0.f) || !isfinite(v)) bad += 1.f;
         else mx = fmaxf(mx, v);
-        alpha[j] = dt * v;
+        alpha[j] = (float)(dt * (double)v);
     }
     smax[threadIdx.x] = mx;
     sbad[threadIdx.x] = bad;
@@ -1021,7 +1025,7 @@ hipError_t launch_batch(int ndim, int order, int64_t nz_any, TileCfg cfg, const 
 
 hipError_t launch_check_fields(const float* m, const float* eta, int64_t rows, int64_t nz,
                                int64_t nzp, float* partial, int nblocks, float* alpha, float* beta,
-                               float dt, hipStream_t s)
+                               double dt, hipStream_t s)
 {
     if (nzp < nz || nzp % 4 != 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_check_fields, dim3(nblocks), dim3(kBlock), 0, s, m, eta, rows, nz, nzp,
@@ -1075,7 +1079,7 @@ hipError_t launch_ckpt_decode(const unsigned short* in_u, const unsigned short* 
 }
 
 hipError_t launch_diffusion_coef(const float* a, int64_t rows, int64_t nz, int64_t nzp,
-                                 float* partial, int nblocks, float* alpha, float* beta, float dt,
+                                 float* partial, int nblocks, float* alpha, float* beta, double dt,
                                  hipStream_t s)
 {
     if (nzp < nz || nzp % 4 != 0) return hipErrorInvalidValue;

@@ -89,7 +89,8 @@ typedef struct {
                                  > 0 = explicit tile id (variant << 16 | x-chunk planes, 0 =
                                  planned).  Variants (block shapes, z x rows of the (y, z)
                                  plane): 2D 0 = 256 z (4 per lane), 1 = 128 z (1 per lane),
-                                 2 = 128 z (2 per lane); 3D 0 = 64 x 16, 1 = 64 x 8,
+                                 2 = 128 z (2 per lane), 3 = 256 z with x-chunks of at most
+                                 16 rows held in LDS; 3D 0 = 64 x 16, 1 = 64 x 8,
                                  2 = 32 x 32, 3 = 100 x 10, 4 = 200 x 5 (4 z-points per
                                  lane), 5 = 64 x 8 (2 per lane).  An unknown variant or a
                                  negative id is WAVE_EINVAL.  Results do not depend on it. */

@@ -83,9 +83,9 @@ inline int tile_id(const TileCfg& c) { return (c.variant << 16) | c.xchunk; }
 // Number of block-shape variants for a grid (2D: 3, 3D: 6; the row length
 // handed to the kernels is always a multiple of 4).
 int tile_variants(int ndim, int64_t nz);
-// Block shape used when no tile is given or cached: in 3D the one whose
-// tiles waste the fewest lanes on the (ny, nz) plane, ties broken by a
-// measured preference order that depends on the space order.
+// Block shape used when no tile is given or cached: in 2D the slab body; in
+// 3D the one whose tiles waste the fewest lanes on the (ny, nz) plane, ties
+// broken by a measured preference order that depends on the space order.
 int default_variant(int ndim, int order, int64_t ny, int64_t nz);
 // Fill the tiling fields of `a` (ntz, nty, xchunk, stencil_blocks, remap) for
 // `cfg`; returns the block count of one launch including receiver samplers.

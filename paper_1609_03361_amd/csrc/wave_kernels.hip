@@ -137,12 +137,87 @@ struct Tile {
     // L2.  Above R = 6 the extra registers would cost occupancy.
     static constexpr bool LEAD = DIM == 3 && R <= 6;
     static constexpr bool HINT = !LEAD;
+    // 2D with TY > 1: the slab body (TY waves share one x-chunk held in LDS)
+    static constexpr bool SLAB = DIM == 2 && TY > 1;
 };
+
+// Rows of u^n a 2D slab block computes at most (its x-chunk); the LDS slab
+// holds them with R halo rows on either side.
+constexpr int kSlabRows = 16;
+
+// z part of the Laplacian for the VZ points of one lane.  `Lc` points at the
+// lane's first point in an LDS row that holds RZ halo points on either side.
+template <int R, int VZ, int RZ>
+__device__ __forceinline__ void z_terms(const float* Lc, const Vec<VZ>& c, const float* m2c,
+                                        const float* cz, float* lap)
+{
+    float zr[2 * RZ + VZ];
+#pragma unroll
+    for (int k = 0; k < RZ / VZ; ++k) {
+        const Vec<VZ> lv = vload<VZ>(Lc - RZ + k * VZ);
+        const Vec<VZ> rv = vload<VZ>(Lc + VZ + k * VZ);
+#pragma unroll
+        for (int v = 0; v < VZ; ++v) {
+            zr[k * VZ + v] = lv[v];
+            zr[RZ + VZ + k * VZ + v] = rv[v];
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < VZ; ++v) zr[RZ + v] = c[v];
+#pragma unroll
+    for (int j = 1; j <= R; ++j)
+#pragma unroll
+        for (int v = 0; v < VZ; ++v)
+            lap[v] = fmaf(cz[j], (zr[RZ + v + j] + zr[RZ + v - j]) + m2c[v], lap[v]);
+}
+
+// The leapfrog update of the VZ points of one lane, then the owner-gather
+// injection of the sources on row (x, y) (only when the block's x-range holds
+// any, `inj_any`, and plane x does).
+template <int VZ>
+__device__ __forceinline__ Vec<VZ> update_inject(const StepArgs& a, const Vec<VZ>& c, const float* lap,
+                                                 const Vec<VZ>& uo, const Vec<VZ>& al, const Vec<VZ>& be,
+                                                 bool inj_any, bool own, int64_t x, int64_t y, int64_t z)
+{
+    Vec<VZ> o;
+#pragma unroll
+    for (int v = 0; v < VZ; ++v) {
+        const float w = fmaf(be[v], c[v] - uo[v], c[v]);
+        o[v] = fmaf(al[v], lap[v], w);
+    }
+    if (inj_any) {
+        // planes without injected nodes skip the per-row lookup (uniform test)
+        const int64_t ny = a.ny;
+        const int32_t* rp = a.inj.row_ptr;
+        if (rp[(x + 1) * ny] != rp[x * ny] && own) {
+            const int64_t row = x * ny + y;
+            const int32_t e0 = rp[row], e1 = rp[row + 1];
+            float acc[VZ];
+            bool hit[VZ];
+#pragma unroll
+            for (int v = 0; v < VZ; ++v) { acc[v] = 0.f; hit[v] = false; }
+            for (int32_t e = e0; e < e1; ++e) {
+                const InjEntry en = a.inj.ent[e];
+                const int64_t dz = (int64_t)en.z - z;
+#pragma unroll
+                for (int v = 0; v < VZ; ++v)
+                    if (dz == v) {
+                        acc[v] = fmaf(en.w, a.inj_val[en.pt], acc[v]);
+                        hit[v] = true;
+                    }
+            }
+#pragma unroll
+            for (int v = 0; v < VZ; ++v)
+                if (hit[v]) o[v] = fmaf(al[v], acc[v], o[v]);
+        }
+    }
+    return o;
+}
 
 // One block's share of one time step: tile (tzi, tyi) of the (y, z) plane over
 // x-chunk `chunk`, where L = (chunk * nty + tyi) * ntz + tzi.
 template <int DIM, int R, int VZ, int TZL, int TY, bool IMG>
-__device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
+__device__ __forceinline__ void stream_body(const StepArgs& a, int64_t L)
 {
     using T = Tile<DIM, R, VZ, TZL, TY>;
     constexpr int NT = T::NT, TZ = T::TZ, RZ = T::RZ, PITCH = T::PITCH, S = T::S, KH = T::KH;
@@ -306,57 +381,8 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
                     lap[v] = fmaf(a.cy[j], (p[v] + m[v]) + m2c[v], lap[v]);
             }
         }
-        {
-            float zr[2 * RZ + VZ];
-#pragma unroll
-            for (int k = 0; k < RZ / VZ; ++k) {
-                const Vec<VZ> lv = vload<VZ>(Ls + row_c - RZ + k * VZ);
-                const Vec<VZ> rv = vload<VZ>(Ls + row_c + VZ + k * VZ);
-#pragma unroll
-                for (int v = 0; v < VZ; ++v) {
-                    zr[k * VZ + v] = lv[v];
-                    zr[RZ + VZ + k * VZ + v] = rv[v];
-                }
-            }
-#pragma unroll
-            for (int v = 0; v < VZ; ++v) zr[RZ + v] = c[v];
-#pragma unroll
-            for (int j = 1; j <= R; ++j)
-#pragma unroll
-                for (int v = 0; v < VZ; ++v)
-                    lap[v] = fmaf(a.cz[j], (zr[RZ + v + j] + zr[RZ + v - j]) + m2c[v], lap[v]);
-        }
-        Vec<VZ> o;
-#pragma unroll
-        for (int v = 0; v < VZ; ++v) {
-            const float w = fmaf(P.be[v], c[v] - P.uo[v], c[v]);
-            o[v] = fmaf(P.al[v], lap[v], w);
-        }
-        if (inj_any) {
-            // planes without injected nodes skip the per-row lookup (uniform test)
-            const int32_t* rp = a.inj.row_ptr;
-            if (rp[(x + 1) * ny] != rp[x * ny] && own) {
-                const int64_t row = x * ny + y;
-                const int32_t e0 = rp[row], e1 = rp[row + 1];
-                float acc[VZ];
-                bool hit[VZ];
-#pragma unroll
-                for (int v = 0; v < VZ; ++v) { acc[v] = 0.f; hit[v] = false; }
-                for (int32_t e = e0; e < e1; ++e) {
-                    const InjEntry en = a.inj.ent[e];
-                    const int64_t dz = (int64_t)en.z - z;
-#pragma unroll
-                    for (int v = 0; v < VZ; ++v)
-                        if (dz == v) {
-                            acc[v] = fmaf(en.w, a.inj_val[en.pt], acc[v]);
-                            hit[v] = true;
-                        }
-                }
-#pragma unroll
-                for (int v = 0; v < VZ; ++v)
-                    if (hit[v]) o[v] = fmaf(P.al[v], acc[v], o[v]);
-            }
-        }
+        z_terms<R, VZ, RZ>(Ls + row_c, c, m2c, a.cz, lap);
+        const Vec<VZ> o = update_inject<VZ>(a, c, lap, P.uo, P.al, P.be, inj_any, own, x, y, z);
         if (own) {
             const int64_t off = x * sx + col;
             if constexpr (IMG) {
@@ -378,6 +404,110 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
             ((go = go && (i + Us < count), go ? (plane(std::integral_constant<int, Us>{}, i + Us), 0) : 0), ...);
         }(std::make_integer_sequence<int, S>{});
     }
+}
+
+// 2D slab body.  The block owns a z-tile of TZ points over an x-chunk of at
+// most kSlabRows rows (16: 32 rows read 1.25 rows per row but ran 5-10 %
+// slower, with fewer blocks resident).  It loads rows xa-R .. xb+R-1 of u^n (with the z halo)
+// into LDS once, and the previous level, alpha and beta of its own points into
+// registers, meets at one barrier, and then each wave computes rows
+// tw, tw + TW, ... of the chunk.  Against the streaming body the halo rows
+// are read once per chunk instead of filling a register queue per lane, and a
+// chunk needs no prologue of its own: 16-row chunks read 24 rows of u^n.  The
+// arithmetic per point is that of the streaming body, term for term, so the
+// two give bitwise the same result.
+template <int R, int VZ, int TZL, int TW, bool IMG>
+__device__ __forceinline__ void slab_body(const StepArgs& a, int64_t L)
+{
+    using T = Tile<2, R, VZ, TZL, TW>;
+    constexpr int NT = T::NT, TZ = T::TZ, RZ = T::RZ, PITCH = T::PITCH;
+    constexpr int XR = kSlabRows, ROWS = XR + 2 * R, NV = PITCH / VZ, RPT = XR / TW;
+    static_assert(XR % TW == 0, "rows per wave must be whole");
+    static_assert(TZL % 64 == 0, "one wave per row group keeps the row test uniform");
+    __shared__ __attribute__((aligned(16))) float lds[ROWS * PITCH];
+
+    const int64_t nx = a.nx, nz = a.nz;
+    const int tid = threadIdx.x;
+    const int tzi = (int)(L % a.ntz);
+    const int64_t chunk = L / a.ntz;        // 2D: one tile row
+    const int tz = tid % TZL, tw = tid / TZL;
+    const int64_t z0 = (int64_t)tzi * TZ, z = z0 + (int64_t)tz * VZ;
+    const bool own = z < nz;
+    const int64_t xa = chunk * a.xchunk;
+    const int64_t xb = xa + a.xchunk < nx ? xa + a.xchunk : nx;
+    const int count = (int)(xb - xa);       // at most XR (planner)
+    const float* __restrict__ u = a.cur;
+
+    // rows xa-R .. xb+R-1 of u^n with the z halo; zero outside the grid
+    for (int i = tid; i < (count + 2 * R) * NV; i += NT) {
+        const int r = i / NV, k = i - r * NV;
+        const int64_t xx = xa - R + r, zz = z0 - RZ + (int64_t)k * VZ;
+        Vec<VZ> v = vzero<VZ>();
+        if (xx >= 0 && xx < nx && zz >= 0 && zz < nz) v = vload<VZ>(u + xx * nz + zz);
+        vstore<VZ>(lds + r * PITCH + k * VZ, v);
+    }
+    Vec<VZ> uo[RPT], al[RPT], be[RPT], fw[RPT], gr[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = tw + q * TW;
+        uo[q] = al[q] = be[q] = fw[q] = gr[q] = vzero<VZ>();
+        if (own && r < count) {
+            const int64_t off = (xa + r) * nz + z;
+            uo[q] = vload_once<VZ, T::HINT>(a.other + off);
+            al[q] = vload_once<VZ, T::HINT>(a.alpha + off);
+            be[q] = vload_once<VZ, T::HINT>(a.beta + off);
+            if constexpr (IMG) {
+                fw[q] = vload_once<VZ, T::HINT>(a.img_fwd + off);
+                gr[q] = vload_once<VZ, T::HINT>(a.img_grad + off);
+            }
+        }
+    }
+    __syncthreads();
+
+    const bool inj_any = a.inj_val && a.inj.row_ptr[xb] != a.inj.row_ptr[xa];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = tw + q * TW;
+        if (r >= count) break;              // uniform within a wave
+        const int64_t x = xa + r;
+        const float* Lc = lds + (r + R) * PITCH + RZ + tz * VZ;
+        const Vec<VZ> c = vload<VZ>(Lc);
+        float lap[VZ], m2c[VZ];
+#pragma unroll
+        for (int v = 0; v < VZ; ++v) {
+            lap[v] = 0.f;
+            m2c[v] = -2.f * c[v];
+        }
+#pragma unroll
+        for (int j = 1; j <= R; ++j) {
+            const Vec<VZ> p = vload<VZ>(Lc + j * PITCH);
+            const Vec<VZ> m = vload<VZ>(Lc - j * PITCH);
+#pragma unroll
+            for (int v = 0; v < VZ; ++v) lap[v] = fmaf(a.cx[j], (p[v] + m[v]) + m2c[v], lap[v]);
+        }
+        z_terms<R, VZ, RZ>(Lc, c, m2c, a.cz, lap);
+        const Vec<VZ> o = update_inject<VZ>(a, c, lap, uo[q], al[q], be[q], inj_any, own, x, 0, z);
+        if (own) {
+            const int64_t off = x * nz + z;
+            if constexpr (IMG) {
+                Vec<VZ> g = gr[q];
+#pragma unroll
+                for (int v = 0; v < VZ; ++v) {
+                    const float d2 = (uo[q][v] + o[v]) + m2c[v];
+                    g[v] = fmaf(-fw[q][v] * a.inv_dt2, d2, g[v]);
+                }
+                vstore_once<VZ, T::HINT>(a.img_grad + off, g);
+            }
+            vstore_once<VZ, T::HINT>(a.out + off, o);
+        }
+    }
+}
+
+template <int DIM, int R, int VZ, int TZL, int TY, bool IMG>
+__device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
+{
+    if constexpr (Tile<DIM, R, VZ, TZL, TY>::SLAB) slab_body<R, VZ, TZL, TY, IMG>(a, L);
+    else stream_body<DIM, R, VZ, TZL, TY, IMG>(a, L);
 }
 
 // Single shot: blocks [0, stencil_blocks) are tiles, the rest sample receivers.
@@ -508,8 +638,11 @@ struct Cfg {
 
 // Block shapes.  The row length nz is a multiple of 4 (the library pads its
 // fields), so every row starts 16-byte aligned.  2D: one wave with four
-// z-points per lane (256 z), 128 scalar lanes (128 z) or one wave with two
-// z-points per lane (128 z); 3D, four z-points per lane: 64 z x 16 rows,
+// z-points per lane (256 z), 128 scalar lanes (128 z), one wave with two
+// z-points per lane (128 z), or the slab body with eight waves of four-point
+// lanes (256 z, chunks of up to 16 rows held in LDS, two rows per wave;
+// measured against four waves with four rows each: 167 us against 170 us on
+// the 48 batched shots, and 172 us for the streaming body); 3D, four z-points per lane: 64 z x 16 rows,
 // 64 z x 8 rows, 32 z x 32 rows, 100 z x 10 rows or 200 z x 5 rows (the
 // last two cover grids such as 200^3 without a mostly empty last tile); 3D,
 // two z-points per lane: 64 z x 8 rows (half the queue registers per lane).
@@ -520,6 +653,7 @@ hipError_t with_shape(int variant, int64_t nz, F&& f)
     if constexpr (DIM == 2) {
         if (variant == 1) return f(Cfg<2, R, 1, 128, 1>{});
         if (variant == 2) return f(Cfg<2, R, 2, 64, 1>{});
+        if (variant == 3) return f(Cfg<2, R, 4, 64, 8>{});
         return f(Cfg<2, R, 4, 64, 1>{});
     } else {
         if (variant == 1) return f(Cfg<3, R, 4, 16, 8>{});
@@ -551,6 +685,7 @@ int64_t plan_t(StepArgs& a, int xchunk, int64_t resident = 0)
     a.ntz = (int32_t)((a.nz + T::TZ - 1) / T::TZ);
     a.nty = C::DIM == 3 ? (int32_t)((a.ny + C::TY - 1) / C::TY) : 1;
     const int64_t tiles = (int64_t)a.ntz * a.nty;
+    if (T::SLAB && xchunk <= 0) xchunk = kSlabRows;   // the longest chunk the slab holds
     if (xchunk <= 0) {
         // 3D: as many blocks as the chip holds at once (`resident`, from the
         // kernel's occupancy; 1024 up to order 12 and 2048 above when
@@ -577,6 +712,7 @@ int64_t plan_t(StepArgs& a, int xchunk, int64_t resident = 0)
         if (xc < xmin) xc = xmin;
         xchunk = (int)(xc < a.nx ? xc : a.nx);
     }
+    if (T::SLAB && xchunk > kSlabRows) xchunk = kSlabRows;
     if (xchunk > a.nx) xchunk = (int)a.nx;
     a.xchunk = xchunk;
     const int64_t nchunk = (a.nx + xchunk - 1) / xchunk;
@@ -902,12 +1038,12 @@ int grid_for(int64_t n)
 
 int tile_variants(int ndim, int64_t)
 {
-    return ndim == 2 ? 3 : 6;
+    return ndim == 2 ? 4 : 6;
 }
 
 int default_variant(int ndim, int order, int64_t ny, int64_t nz)
 {
-    if (ndim == 2) return 0;      // one wave of float4 lanes measured fastest in 2D
+    if (ndim == 2) return 3;      // the slab body (2001 x 801 order 8: 8.7 us against 10.9 us per step)
     // Candidates in order of preference at equal lane waste: up to order 8
     // the two-point-lane tile first (256^3 order 8: 52.2 us against 53.8 us
     // for 64 z x 16 rows of four-point lanes); above, it is slower (512^3

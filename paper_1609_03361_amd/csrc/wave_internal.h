@@ -52,8 +52,9 @@ struct StepArgs {
     float* smp_out;        // [npts] for this step, or nullptr
     int64_t stencil_blocks;
     // streaming-kernel tiling (set by the launcher): tiles along z and y,
-    // x-chunk length, and whether to remap block ids so that consecutive
-    // tiles land on the same XCD
+    // x-chunk length, and whether the single-shot grid pads its tile part to
+    // a multiple of 8 and remaps block ids so that consecutive tiles land on
+    // the same XCD
     int32_t ntz, nty, xchunk, remap;
     // imaging condition (adjoint with gradient): g -= fwd * (other - 2 cur + out) / dt^2
     const float* img_fwd;  // u^k, or nullptr

@@ -510,18 +510,29 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
     else stream_body<DIM, R, VZ, TZL, TY, IMG>(a, L);
 }
 
-// Single shot: blocks [0, stencil_blocks) are tiles, the rest sample receivers.
+// Single shot: the first blocks are tiles, the rest sample receivers.  With
+// `remap` the tile part of the grid is padded to a multiple of 8 and block b
+// takes tile L = (b mod 8) * (part / 8) + b / 8: blocks are dealt to the 8
+// XCDs in turn, so each XCD gets a contiguous run of tiles, and neighbouring
+// tiles and chunks, which read each other's halo, share one L2.  (2001 x 801
+// order 8 with 2D slabs: 6.5 us per step with 504 tiles, 10.0 us with 1004
+// tiles before the padding, which then ran without the remap.)
 template <int DIM, int R, int VZ, int TZL, int TY, bool IMG>
 __global__ __launch_bounds__(TZL* TY) void k_step_stream(StepArgs a)
 {
     const int64_t b = blockIdx.x;
-    if (b >= a.stencil_blocks) {
-        const int64_t p = (b - a.stencil_blocks) * (TZL * TY) + threadIdx.x;
+    const int64_t SB = a.stencil_blocks;
+    const int64_t part = a.remap ? (SB + 7) / 8 * 8 : SB;
+    if (b >= part) {
+        const int64_t p = (b - part) * (TZL * TY) + threadIdx.x;
         if (p < a.smp.npts) a.smp_out[p] = sample_point<DIM>(a.smp, a.cur, p, a.nz, a.ny * a.nz);
         return;
     }
     int64_t L = b;
-    if (a.remap) L = (b & 7) * (a.stencil_blocks >> 3) + (b >> 3);
+    if (a.remap) {
+        L = (b & 7) * (part >> 3) + (b >> 3);
+        if (L >= SB) return;                // padding
+    }
     stream_tile<DIM, R, VZ, TZL, TY, IMG>(a, L);
 }
 
@@ -679,25 +690,15 @@ hipError_t with_cfg(int ndim, int order, int variant, int64_t nz, F&& f)
 }
 
 template <class C>
-int64_t plan_t(StepArgs& a, int xchunk, int64_t resident = 0)
+int64_t plan_t(StepArgs& a, int xchunk, int64_t resident = 0, bool single = false)
 {
     using T = typename C::T;
     a.ntz = (int32_t)((a.nz + T::TZ - 1) / T::TZ);
     a.nty = C::DIM == 3 ? (int32_t)((a.ny + C::TY - 1) / C::TY) : 1;
     const int64_t tiles = (int64_t)a.ntz * a.nty;
-    if (T::SLAB && xchunk <= 0) {
-        // one launch on its own (resident known): about 1024 blocks, so a
-        // small grid still fills the chip (2001 x 801 order 8: 8 rows, 7.5 us
-        // per step against 8.7 us at 16; 1000^2 order 2: 4 rows); inside a
-        // batch, many shots share the launch: the longest chunk the slab holds
-        xchunk = kSlabRows;
-        if (resident > 0) {
-            const int64_t want_chunks = (1024 + tiles - 1) / tiles;
-            int64_t xc = (a.nx + want_chunks - 1) / want_chunks;
-            if (xc < 2 * C::R) xc = 2 * C::R;
-            if (xc < kSlabRows) xchunk = (int)xc;
-        }
-    }
+    // the longest chunk the slab holds (with the XCD remap of single-shot
+    // launches, 16 rows beat 8 on 2001 x 801 order 8: 6.6 us against 7.8 us)
+    if (T::SLAB && xchunk <= 0) xchunk = kSlabRows;
     if (xchunk <= 0) {
         // 3D: as many blocks as the chip holds at once (`resident`, from the
         // kernel's occupancy; 1024 up to order 12 and 2048 above when
@@ -729,10 +730,13 @@ int64_t plan_t(StepArgs& a, int xchunk, int64_t resident = 0)
     a.xchunk = xchunk;
     const int64_t nchunk = (a.nx + xchunk - 1) / xchunk;
     a.stencil_blocks = tiles * nchunk;
-    a.remap = (a.stencil_blocks % 8 == 0) ? 1 : 0;
+    // a single-shot launch pads its tile part to a multiple of 8 and remaps
+    // (k_step_stream); the many-shot kernels index items directly
+    a.remap = single ? 1 : 0;
+    const int64_t part = single ? (a.stencil_blocks + 7) / 8 * 8 : a.stencil_blocks;
     int64_t nsb = 0;
     if (a.smp_out && a.smp.npts > 0) nsb = (a.smp.npts + T::NT - 1) / T::NT;
-    return a.stencil_blocks + nsb;
+    return part + nsb;
 }
 
 // Index of padded element j ([rows][nzp]) in the unpadded caller array
@@ -1116,7 +1120,7 @@ hipError_t launch_step(int ndim, int order, const StepArgs& a0, hipStream_t s, T
         auto launch = [&](auto kern, std::atomic<int64_t>& cache) {
             StepArgs a = a0;
             const int64_t res = cfg.xchunk <= 0 ? resident_blocks(kern, CC::T::NT, cache) : 0;
-            const int64_t blocks = plan_t<CC>(a, cfg.xchunk, res);
+            const int64_t blocks = plan_t<CC>(a, cfg.xchunk, res, true);
             if (!(a.smp_out && a.smp.npts > 0)) a.smp.npts = 0;
             hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(CC::T::NT), 0, s, a);
             return hipGetLastError();

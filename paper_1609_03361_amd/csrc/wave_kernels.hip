@@ -147,6 +147,7 @@ constexpr int kSlabRows = 16;
 
 // z part of the Laplacian for the VZ points of one lane.  `Lc` points at the
 // lane's first point in an LDS row that holds RZ halo points on either side.
+// (Used by the slab body; the streaming body has the same terms inline.)
 template <int R, int VZ, int RZ>
 __device__ __forceinline__ void z_terms(const float* Lc, const Vec<VZ>& c, const float* m2c,
                                         const float* cz, float* lap)
@@ -173,7 +174,9 @@ __device__ __forceinline__ void z_terms(const float* Lc, const Vec<VZ>& c, const
 
 // The leapfrog update of the VZ points of one lane, then the owner-gather
 // injection of the sources on row (x, y) (only when the block's x-range holds
-// any, `inj_any`, and plane x does).
+// any, `inj_any`, and plane x does).  The streaming body spells out the same
+// operations inline (as a call here it held two more registers per lane,
+// which cost a wave per SIMD); the tile tests check the two bit for bit.
 template <int VZ>
 __device__ __forceinline__ Vec<VZ> update_inject(const StepArgs& a, const Vec<VZ>& c, const float* lap,
                                                  const Vec<VZ>& uo, const Vec<VZ>& al, const Vec<VZ>& be,
@@ -381,8 +384,57 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, int64_t L)
                     lap[v] = fmaf(a.cy[j], (p[v] + m[v]) + m2c[v], lap[v]);
             }
         }
-        z_terms<R, VZ, RZ>(Ls + row_c, c, m2c, a.cz, lap);
-        const Vec<VZ> o = update_inject<VZ>(a, c, lap, P.uo, P.al, P.be, inj_any, own, x, y, z);
+        {
+            float zr[2 * RZ + VZ];
+#pragma unroll
+            for (int k = 0; k < RZ / VZ; ++k) {
+                const Vec<VZ> lv = vload<VZ>(Ls + row_c - RZ + k * VZ);
+                const Vec<VZ> rv = vload<VZ>(Ls + row_c + VZ + k * VZ);
+#pragma unroll
+                for (int v = 0; v < VZ; ++v) {
+                    zr[k * VZ + v] = lv[v];
+                    zr[RZ + VZ + k * VZ + v] = rv[v];
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < VZ; ++v) zr[RZ + v] = c[v];
+#pragma unroll
+            for (int j = 1; j <= R; ++j)
+#pragma unroll
+                for (int v = 0; v < VZ; ++v)
+                    lap[v] = fmaf(a.cz[j], (zr[RZ + v + j] + zr[RZ + v - j]) + m2c[v], lap[v]);
+        }
+        Vec<VZ> o;
+#pragma unroll
+        for (int v = 0; v < VZ; ++v) {
+            const float w = fmaf(P.be[v], c[v] - P.uo[v], c[v]);
+            o[v] = fmaf(P.al[v], lap[v], w);
+        }
+        if (inj_any) {
+            // planes without injected nodes skip the per-row lookup (uniform test)
+            const int32_t* rp = a.inj.row_ptr;
+            if (rp[(x + 1) * ny] != rp[x * ny] && own) {
+                const int64_t row = x * ny + y;
+                const int32_t e0 = rp[row], e1 = rp[row + 1];
+                float acc[VZ];
+                bool hit[VZ];
+#pragma unroll
+                for (int v = 0; v < VZ; ++v) { acc[v] = 0.f; hit[v] = false; }
+                for (int32_t e = e0; e < e1; ++e) {
+                    const InjEntry en = a.inj.ent[e];
+                    const int64_t dz = (int64_t)en.z - z;
+#pragma unroll
+                    for (int v = 0; v < VZ; ++v)
+                        if (dz == v) {
+                            acc[v] = fmaf(en.w, a.inj_val[en.pt], acc[v]);
+                            hit[v] = true;
+                        }
+                }
+#pragma unroll
+                for (int v = 0; v < VZ; ++v)
+                    if (hit[v]) o[v] = fmaf(P.al[v], acc[v], o[v]);
+            }
+        }
         if (own) {
             const int64_t off = x * sx + col;
             if constexpr (IMG) {
@@ -414,8 +466,8 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, int64_t L)
 // tw, tw + TW, ... of the chunk.  Against the streaming body the halo rows
 // are read once per chunk instead of filling a register queue per lane, and a
 // chunk needs no prologue of its own: 16-row chunks read 24 rows of u^n.  The
-// arithmetic per point is that of the streaming body, term for term, so the
-// two give bitwise the same result.
+// arithmetic per point is that of the streaming body, term for term and in
+// the same order, so the two give bitwise the same result.
 template <int R, int VZ, int TZL, int TW, bool IMG>
 __device__ __forceinline__ void slab_body(const StepArgs& a, int64_t L)
 {

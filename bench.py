@@ -7,8 +7,15 @@ sampling), inputs resident in HBM.  Prints one JSON line.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
 Workloads (seeded synthetic layered models, sponge, Ricker source):
-  3d-256-o8   256^3, space order 8, 1000 steps, 128x128 receivers (default)
-  3d-512-o16  512^3, space order 16, 2000 steps, 256x256 receivers
+  3d-256-o8   256^3, space order 8, 1000 steps, 128x128 receivers (default;
+              `value` is this one)
+  3d-512-o16  512^3, space order 16, 2000 steps, 256x256 receivers (the
+              roofline benchmark; also reported as its own leg of the default
+              run, with its own roofline block)
+Further legs of the default run: the FWI gradient (200^3, checkpointed,
+FP32/BF16/FP16 snapshots) against the plain forward, 48 batched 2D shots
+against the single-shot path, the paper's diffusion example, and the CPU
+oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -37,18 +44,68 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+STEP_SOURCES = ("wave_step.h", "wave_internal.h")
+
+
+def step_kernel_sha():
+    """Hash of the step kernel's sources (the templates and the argument layout)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in STEP_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1609_03361_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(workload):
     """HBM bytes per step launch from the committed rocprofv3 --pmc summary
     (FETCH_SIZE and WRITE_SIZE scaled by the plain-copy calibration), or None
     when the step kernel's source has changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
-    src = os.path.join(ROOT, "paper_1609_03361_amd", "csrc", "wave_kernels.hip")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    return rec["hbm_bytes_per_launch"] if rec.get("kernel_source_sha256_16") == sha else None
+    return rec["hbm_bytes_per_launch"] if rec.get("kernel_source_sha256_16") == step_kernel_sha() else None
+
+
+def forward_leg(dev, p, steps, warmup, tile=0):
+    """Time `steps` forward runs of problem p (after `warmup`): whole-job
+    Gpts/s from torch events around the runs, and the step kernel's average
+    launch time from the library's HIP events around each time loop (on the
+    stream the kernel runs on)."""
+    import torch
+    from paper_1609_03361_amd import api, _lib
+    geom = api.Geometry(p.shape, p.spacing, p.order, p.dt, p.nt, p.src, p.rec)
+    m = torch.from_numpy(p.m).to(dev)
+    eta = torch.from_numpy(p.eta).to(dev)
+    q = torch.from_numpy(p.q).to(dev)
+    for _ in range(warmup):
+        api.forward(geom, m, eta, q, tile=tile)
+    torch.cuda.synchronize()
+    _lib.set_profiling(True)
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    loop_ms, launches = 0.0, 0
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        api.forward(geom, m, eta, q, tile=tile)
+        ms, n = _lib.last_loop()          # waits for this run's loop to end
+        loop_ms += ms
+        launches += n
+    e1.record(stream)
+    torch.cuda.synchronize()
+    _lib.set_profiling(False)
+    total_ms = e0.elapsed_time(e1)
+    per_launch_ms = loop_ms / launches
+    alg_bytes = BYTES_PER_UPDATE * p.npoints
+    achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(p.name) if tile == 0 else None,
+            "kernel": "leapfrog step", "launch_ms": round(per_launch_ms, 5),
+            "alg_bytes_per_launch": alg_bytes, "tile": api.resolve_tile(geom, tile)}
+    return total_ms, roof
 
 
 def cpu_baseline(p, steps):
@@ -163,6 +220,7 @@ def batched_bench(dev, reps=2):
             "mode": "per-step launches over all shots, replayed from a hipGraph",
             "persistent_single_launch_s": round(tp, 4),
             "tile": {"variant": tile >> 16, "xchunk": tile & 0xffff, "tuned_us_per_step": round(tune_us, 2)},
+            "persistent_mode": api.last_batch_mode(),
             "single_shot_full_model_gpts": round(single, 2),
             "batched_vs_single": round(batched / single, 3)}
 
@@ -200,9 +258,12 @@ def main():
                     help="skip the FWI-gradient seconds-per-shot measurement")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched multi-shot measurement")
+    ap.add_argument("--no-o16", action="store_true",
+                    help="skip the 512^3 order-16 leg")
     ap.add_argument("--nt", type=int, default=0,
                     help="override the number of time steps (for short profiler runs)")
-    ap.add_argument("--tile", type=int, default=0, help="x-chunk length (0 = automatic)")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="tile id of the main leg (variant << 16 | x-chunk; 0 = tuned or automatic)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 10 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -215,46 +276,17 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1609_03361_amd import api, _lib
 
     dev = torch.device("cuda:0")
     p = make_workload(args.workload)
     if args.nt > 0:
         p.nt = args.nt
         p.q = p.q[: args.nt].copy()
-    geom = api.Geometry(p.shape, p.spacing, p.order, p.dt, p.nt, p.src, p.rec)
-    m = torch.from_numpy(p.m).to(dev)
-    eta = torch.from_numpy(p.eta).to(dev)
-    q = torch.from_numpy(p.q).to(dev)
     print(f"# workload {p.name}: shape {p.shape} order {p.order} nt {p.nt} "
           f"nrec {p.rec.shape[0]}", file=sys.stderr, flush=True)
-
-    for _ in range(args.warmup):
-        api.forward(geom, m, eta, q, tile=args.tile)
-    torch.cuda.synchronize()
-
-    _lib.set_profiling(True)
-    stream = torch.cuda.current_stream(dev)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    loop_ms, launches = 0.0, 0
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        api.forward(geom, m, eta, q, tile=args.tile)
-        ms, n = _lib.last_loop()          # waits for this run's loop to end
-        loop_ms += ms
-        launches += n
-    e1.record(stream)
-    torch.cuda.synchronize()
-    _lib.set_profiling(False)
-    total_ms = e0.elapsed_time(e1)
-
+    total_ms, roof = forward_leg(dev, p, args.steps, args.warmup, args.tile)
     updates = p.npoints * p.nt * args.steps
     value = updates / (total_ms * 1e-3) / 1e9
-    per_launch_ms = loop_ms / launches
-    alg_bytes = BYTES_PER_UPDATE * p.npoints
-    achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -272,12 +304,19 @@ def main():
                    "time_steps": p.nt, "receivers": int(p.rec.shape[0]), "sources": 1,
                    "bench_step": "one full forward modelling run"},
         "hbm_roofline_frac": round(value * BYTES_PER_UPDATE / HBM_PEAK_GBS, 4),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(p.name) if args.tile == 0 else None,
-                     "kernel": "leapfrog step", "launch_ms": round(per_launch_ms, 5),
-                     "alg_bytes_per_launch": alg_bytes},
+        "roofline": roof,
     }
+    if args.workload == "3d-256-o8" and not args.no_o16 and args.nt == 0:
+        # the roofline benchmark: 512^3, order 16, 2000 steps, timed the same way
+        p16 = make_workload("3d-512-o16")
+        print(f"# workload {p16.name}: shape {p16.shape} order {p16.order} nt {p16.nt}",
+              file=sys.stderr, flush=True)
+        ms16, roof16 = forward_leg(dev, p16, 2, 1)
+        out["order16_512"] = {"workload": p16.name, "time_steps": p16.nt,
+                              "ms_per_run": round(ms16 / 2, 3),
+                              "gpts": round(p16.npoints * p16.nt * 2 / (ms16 * 1e-3) / 1e9, 3),
+                              "roofline": roof16}
+        del p16
     if not args.no_gradient:
         out["fwi_gradient"] = gradient_bench(dev)
     if not args.no_batched:

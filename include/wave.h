@@ -97,13 +97,18 @@ typedef struct {
     int32_t flags;            /* WAVE_FLAG_* bits */
 } wave_opts;
 
-#define WAVE_FLAG_NO_GRAPH 1    /* batch: launch the steps one by one instead of replaying a hipGraph */
+#define WAVE_FLAG_NO_GRAPH 1    /* batch: launch directly instead of replaying a hipGraph */
 #define WAVE_FLAG_PERSISTENT 2  /* batch: one persistent co-resident launch for all steps (see below) */
+#define WAVE_FLAG_TUNE_IMAGING 4 /* wave_tune (and the workspace size of WAVE_OP_FORWARD): time
+                                    the adjoint step with the imaging condition instead of the
+                                    plain step; the result is cached for that kernel only */
 
 typedef enum {
-    WAVE_OP_FORWARD = 0,      /* wave_forward (no checkpoints) */
+    WAVE_OP_FORWARD = 0,      /* wave_forward without checkpoints, wave_diffusion, wave_tune */
     WAVE_OP_ADJOINT = 1,      /* wave_adjoint */
-    WAVE_OP_GRADIENT = 2,     /* wave_gradient, wave_backward, wave_forward with checkpoints */
+    WAVE_OP_GRADIENT = 2,     /* wave_gradient (includes the checkpoint storage) */
+    WAVE_OP_FORWARD_CKPT = 3, /* wave_forward writing caller-owned checkpoints */
+    WAVE_OP_BACKWARD = 4,     /* wave_backward (replay ring, adjoint pair, gradient accumulator) */
 } wave_op;
 
 /* Bytes of workspace an entry point needs for this grid and point sets
@@ -131,9 +136,11 @@ int wave_checkpoint_size(const wave_grid* grid, const wave_opts* opts, size_t* b
  *   src, q          source positions and wavelets q [nt][nsrc]
  *   rec, d          receiver positions and traces d [nt][nrec] (written; d^n from u^n)
  *   u_final         NULL or [shape]: receives u^nt
- *   ckpt            NULL, or checkpoint storage of wave_checkpoint_size()
- *                   bytes: receives the (u^c, u^{c-1}) pairs that
- *                   wave_backward replays
+ *   ckpt            NULL, or DEVICE checkpoint storage of at least
+ *                   wave_checkpoint_size() bytes for the same opts->ckpt_every
+ *                   and ckpt_dtype (the library cannot check its size):
+ *                   receives the snapshots that wave_backward replays
+ * Workspace: op WAVE_OP_FORWARD, or WAVE_OP_FORWARD_CKPT when ckpt is given.
  */
 int wave_forward(const wave_grid* grid, const float* m, const float* eta,
                  const wave_points* src, const float* q,
@@ -163,7 +170,7 @@ int wave_adjoint(const wave_grid* grid, const float* m, const float* eta,
  *                       with v the adjoint field driven by r (eta held fixed)
  *   grad_q [nt][nsrc]   NULL or written: dJ/dq (the adjoint sampled at the sources)
  * `ckpt` must come from wave_forward with the same grid, fields, sources,
- * wavelets and opts->ckpt_every/ckpt_dtype.
+ * wavelets and opts->ckpt_every/ckpt_dtype.  Workspace: op WAVE_OP_BACKWARD.
  */
 int wave_backward(const wave_grid* grid, const float* m, const float* eta,
                   const wave_points* src, const float* q,
@@ -211,10 +218,15 @@ typedef struct {
 int wave_batch_workspace_size(int32_t nshots, const wave_shot* shots, const wave_opts* opts,
                               size_t* bytes);
 /* With opts->flags & WAVE_FLAG_PERSISTENT the whole time loop of all shots is
- * one cooperative launch (the runtime guarantees that all its blocks are
- * resident at once), with a device-wide barrier between steps.  That mode
- * waits for the launch before returning and reports WAVE_EHIP if a barrier
- * wait ever exceeded its bound. */
+ * one cooperative launch (all its blocks are resident at once; the grid is
+ * what the kernel's occupancy allows), with a device-wide barrier between
+ * steps.  By default that launch is the cooperative kernel node of a hipGraph
+ * (built once and reused like the per-step graph); with WAVE_FLAG_NO_GRAPH as
+ * well it is a direct cooperative launch.  The persistent mode waits for the
+ * launch before returning and reports WAVE_EHIP if a barrier wait ever
+ * exceeded its bound (every wait is bounded, so the launch always ends).
+ * In every mode the blocks of the larger shots come first in the flattened
+ * list; the order does not change any result. */
 int wave_forward_batch(int32_t nshots, const wave_shot* shots, const wave_opts* opts, void* stream);
 /* How this thread's last wave_forward_batch ran: 0 per-step launches replayed
  * from a hipGraph, 1 per-step launches, 2 one persistent launch, 3 one
@@ -236,6 +248,17 @@ int wave_tune(const wave_grid* grid, const wave_opts* opts, int32_t steps, void*
 int wave_tune_batch(int32_t nshots, const wave_shot* shots, const wave_opts* opts, int32_t steps,
                     void* stream, int32_t* tile, double* us_per_step);
 
+/* The tile ids wave_tune times on this grid, in order: every block shape with
+ * x-chunks of 2R, 4R, 8, 16, ..., 128 planes, each clamped to what the shape
+ * accepts and to the grid, so no two ids launch the same thing.  Writes up
+ * to `cap` ids into `ids` and the number of candidates into *n.  Host only. */
+int wave_tile_candidates(const wave_grid* grid, int32_t* ids, int32_t cap, int32_t* n);
+/* The tile a step launch on this grid uses for the requested id (0 = the
+ * tuned or default one): its block shape and its x-chunk after clamping and
+ * planning.  For an x-chunk of 0 the plan is the one made without the
+ * device's occupancy figure, which a launch may refine.  Host only. */
+int wave_resolve_tile(const wave_grid* grid, int32_t tile, int32_t* resolved);
+
 /*
  * Diffusion (Section "2D Diffusion Example", equation "eqn:diffusion"):
  * u_t = a lap(u) with forward Euler in time, the same order-2k Laplacian and
@@ -249,6 +272,20 @@ int wave_tune_batch(int32_t nshots, const wave_shot* shots, const wave_opts* opt
 int wave_diffusion(const wave_grid* grid, const float* a, const float* u0, float* u_final,
                    const wave_opts* opts, void* stream);
 
+/*
+ * Misfit of modelled against observed data (the objective of the gradient
+ * test, Section "Performance" of the seismic example): r = d - d_obs and
+ * J = 1/2 sum r^2, summed in a fixed order (per-block partial sums, then one
+ * block), so the result is run-to-run reproducible.
+ *   d, d_obs  DEVICE [n] FP32
+ *   r         NULL or DEVICE [n]: receives the residual
+ *   misfit    DEVICE, one float: receives J
+ *   opts      workspace of at least WAVE_MISFIT_WORKSPACE_BYTES bytes (partials)
+ */
+#define WAVE_MISFIT_WORKSPACE_BYTES 4096
+int wave_misfit(const float* d, const float* d_obs, int64_t n, float* r, float* misfit,
+                const wave_opts* opts, void* stream);
+
 /* Phase timing (a metrics aid).  With profiling on, each entry point called
  * by this thread records HIP events on its stream around its time loop(s),
  * from the first step launch to the last (set-up excluded).
@@ -256,6 +293,14 @@ int wave_diffusion(const wave_grid* grid, const float* a, const float* u0, float
  * elapsed milliseconds and the number of step launches it made. */
 int wave_set_profiling(int32_t enable);
 int wave_last_loop(double* ms, int64_t* launches);
+
+/* Releases what the library keeps for the calling thread: the last
+ * instantiated batch graph and its capture stream, the timing events and the
+ * pinned host staging buffer (after its last copy has finished).  Later calls
+ * recreate them on demand.  Call it before the HIP runtime shuts down (the
+ * Python binding does so at interpreter exit); returns WAVE_EHIP if the
+ * runtime refused a release. */
+int wave_release(void);
 
 /* Thread-local message describing the last non-zero return ("" if none). */
 const char* wave_last_error(void);

@@ -6,6 +6,7 @@ implementation behind these names.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 
@@ -15,7 +16,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_build", "libwave.so")
 
 WAVE_OK, WAVE_EINVAL, WAVE_ECFL, WAVE_ERANGE, WAVE_EWORKSPACE, WAVE_EHIP = 0, -1, -2, -3, -4, -5
-WAVE_OP_FORWARD, WAVE_OP_ADJOINT, WAVE_OP_GRADIENT = 0, 1, 2
+WAVE_OP_FORWARD, WAVE_OP_ADJOINT, WAVE_OP_GRADIENT, WAVE_OP_FORWARD_CKPT, WAVE_OP_BACKWARD = \
+    0, 1, 2, 3, 4
+WAVE_MISFIT_WORKSPACE_BYTES = 4096
 CKPT_DTYPES = {"fp32": 0, "bf16": 1, "fp16": 2}
 _NAMES = {0: "WAVE_OK", -1: "WAVE_EINVAL", -2: "WAVE_ECFL", -3: "WAVE_ERANGE",
           -4: "WAVE_EWORKSPACE", -5: "WAVE_EHIP"}
@@ -23,11 +26,12 @@ _NAMES = {0: "WAVE_OK", -1: "WAVE_EINVAL", -2: "WAVE_ECFL", -3: "WAVE_ERANGE",
 EXPORTS = ["wave_workspace_size", "wave_checkpoint_size", "wave_forward", "wave_adjoint",
            "wave_backward", "wave_gradient", "wave_batch_workspace_size", "wave_forward_batch",
            "wave_tune", "wave_tune_batch", "wave_last_batch_mode", "wave_diffusion",
-           "wave_set_profiling",
-           "wave_last_loop",
+           "wave_set_profiling", "wave_last_loop", "wave_misfit", "wave_release",
+           "wave_tile_candidates", "wave_resolve_tile",
            "wave_last_error", "wave_version"]
 WAVE_FLAG_NO_GRAPH = 1
 WAVE_FLAG_PERSISTENT = 2
+WAVE_FLAG_TUNE_IMAGING = 4
 
 
 class WaveError(RuntimeError):
@@ -93,10 +97,27 @@ def lib():
         L.wave_last_batch_mode.restype = C.c_int
         L.wave_diffusion.argtypes = [P(Grid), VP, VP, VP, P(Opts), VP]
         L.wave_diffusion.restype = C.c_int
+        L.wave_misfit.argtypes = [VP, VP, C.c_int64, VP, VP, P(Opts), VP]
+        L.wave_misfit.restype = C.c_int
+        L.wave_tile_candidates.argtypes = [P(Grid), P(C.c_int32), I32, P(C.c_int32)]
+        L.wave_tile_candidates.restype = C.c_int
+        L.wave_resolve_tile.argtypes = [P(Grid), I32, P(C.c_int32)]
+        L.wave_resolve_tile.restype = C.c_int
+        L.wave_release.argtypes = []
+        L.wave_release.restype = C.c_int
         L.wave_last_error.restype = C.c_char_p
         L.wave_version.restype = C.c_char_p
         _lib = L
+        # release the library's per-thread HIP objects (graph, capture stream,
+        # events, pinned staging) before the runtime itself shuts down
+        atexit.register(release)
     return _lib
+
+
+def release() -> None:
+    """Destroy what libwave.so keeps for the calling thread (see wave_release)."""
+    if _lib is not None:
+        _lib.wave_release()
 
 
 def check(rc: int, where: str) -> None:

@@ -20,7 +20,8 @@ import torch
 from . import _lib as L
 
 __all__ = ["Geometry", "forward", "adjoint", "backward", "gradient", "checkpoint_bytes",
-           "forward_batch", "tune", "tune_batch", "diffusion", "WaveFn", "wave_apply"]
+           "forward_batch", "tune", "tune_batch", "tile_candidates", "resolve_tile", "diffusion",
+           "misfit", "WaveFn", "wave_apply"]
 
 
 def _ptr(t):
@@ -34,6 +35,16 @@ def _need(t, name, shape=None):
         raise ValueError(f"{name} must be a contiguous float32 device tensor")
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _need_checkpoint(ck, geom, ckpt_every, ckpt_dtype):
+    """The library cannot see the size of the checkpoint buffer: check it here."""
+    if not (ck.is_cuda and ck.dtype == torch.uint8 and ck.is_contiguous()):
+        raise ValueError("checkpoint must be a contiguous uint8 device tensor")
+    need = checkpoint_bytes(geom, ckpt_every, ckpt_dtype)
+    if ck.numel() < need:
+        raise ValueError(f"checkpoint holds {ck.numel()} bytes; ckpt_every={ckpt_every}, "
+                         f"ckpt_dtype={ckpt_dtype} need {need}")
 
 
 def _stream(dev):
@@ -92,7 +103,10 @@ def forward(geom: Geometry, m, eta=None, q=None, return_final=False, checkpoint=
     dev = m.device
     grid = geom.grid()
     kw = dict(ckpt_every=ckpt_every, ckpt_dtype=ckpt_dtype, tile=tile)
-    op = L.WAVE_OP_GRADIENT if checkpoint is not None else L.WAVE_OP_FORWARD
+    op = L.WAVE_OP_FORWARD
+    if checkpoint is not None:
+        _need_checkpoint(checkpoint, geom, ckpt_every, ckpt_dtype)
+        op = L.WAVE_OP_FORWARD_CKPT
     ws, o = _workspace(op, grid, sp, rp, kw, dev)
     d = torch.empty((geom.nt, rp.npts), dtype=torch.float32, device=dev)
     uf = torch.empty(geom.shape, dtype=torch.float32, device=dev) if return_final else None
@@ -126,10 +140,11 @@ def backward(geom: Geometry, m, eta, q, r, checkpoint, ckpt_every=0, ckpt_dtype=
     _need(eta, "eta", geom.shape)
     sp, rp = geom.points()
     _need(r, "r", (geom.nt, rp.npts))
+    _need_checkpoint(checkpoint, geom, ckpt_every, ckpt_dtype)
     dev = m.device
     grid = geom.grid()
     kw = dict(ckpt_every=ckpt_every, ckpt_dtype=ckpt_dtype, tile=tile)
-    ws, o = _workspace(L.WAVE_OP_GRADIENT, grid, sp, rp, kw, dev)
+    ws, o = _workspace(L.WAVE_OP_BACKWARD, grid, sp, rp, kw, dev)
     g = torch.empty(geom.shape, dtype=torch.float32, device=dev)
     gq = torch.empty((geom.nt, sp.npts), dtype=torch.float32, device=dev) \
         if (want_grad_q and sp.npts) else None
@@ -164,13 +179,34 @@ def tile_id(variant: int, xchunk: int) -> int:
     return (int(variant) << 16) | int(xchunk)
 
 
-def tune(geom: Geometry, steps: int = 20, device=None):
+def tile_candidates(geom: Geometry):
+    """Tile ids the autotuner times on this grid (distinct launches)."""
+    grid = geom.grid()
+    n = C.c_int32(0)
+    L.check(L.lib().wave_tile_candidates(C.byref(grid), None, 0, C.byref(n)), "wave_tile_candidates")
+    ids = (C.c_int32 * max(n.value, 1))()
+    L.check(L.lib().wave_tile_candidates(C.byref(grid), ids, n.value, C.byref(n)),
+            "wave_tile_candidates")
+    return [int(ids[i]) for i in range(n.value)]
+
+
+def resolve_tile(geom: Geometry, tile: int = 0) -> int:
+    """The tile id a step launch on this grid uses for the requested one."""
+    grid = geom.grid()
+    out = C.c_int32(0)
+    L.check(L.lib().wave_resolve_tile(C.byref(grid), int(tile), C.byref(out)), "wave_resolve_tile")
+    return int(out.value)
+
+
+def tune(geom: Geometry, steps: int = 20, device=None, imaging=False):
     """Time every candidate tile on this grid; returns (tile id, us per step).
-    The winner is cached for later calls with tile=0."""
+    The winner is cached for later calls with tile=0; with ``imaging`` the
+    adjoint step with the imaging condition is tuned (and cached) instead."""
     dev = torch.device(device or "cuda:0")
     grid = geom.grid()
     empty = L.HostPoints(None, len(geom.shape))
-    ws, o = _workspace(L.WAVE_OP_FORWARD, grid, empty, empty, {}, dev)
+    flags = L.WAVE_FLAG_TUNE_IMAGING if imaging else 0
+    ws, o = _workspace(L.WAVE_OP_FORWARD, grid, empty, empty, dict(flags=flags), dev)
     t = C.c_int32(0)
     us = C.c_double(0)
     L.check(L.lib().wave_tune(C.byref(grid), C.byref(o), int(steps), _stream(dev), C.byref(t),
@@ -230,8 +266,26 @@ def forward_batch(shots, return_final=False, tile=0, graph=True, persistent=Fals
 
 
 def last_batch_mode() -> int:
-    """0: per-step graph, 1: per-step launches, 2: persistent, 3: persistent in a graph."""
+    """How the last forward_batch on this thread ran: 0 per-step launches
+    replayed from a hipGraph, 1 per-step launches, 2 one persistent launch,
+    3 one persistent launch replayed from a hipGraph."""
     return int(L.lib().wave_last_batch_mode())
+
+
+def misfit(d, d_obs, return_residual=False):
+    """J = 1/2 sum (d - d_obs)^2 as a device scalar (wave_misfit), and the
+    residual r = d - d_obs if ``return_residual``."""
+    _need(d, "d")
+    _need(d_obs, "d_obs", tuple(d.shape))
+    dev = d.device
+    ws = torch.empty(L.WAVE_MISFIT_WORKSPACE_BYTES + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    o = L.make_opts(ws.data_ptr() + off, L.WAVE_MISFIT_WORKSPACE_BYTES)
+    J = torch.empty((), dtype=torch.float32, device=dev)
+    r = torch.empty_like(d) if return_residual else None
+    L.check(L.lib().wave_misfit(_ptr(d), _ptr(d_obs), d.numel(), _ptr(r), _ptr(J), C.byref(o),
+                                _stream(dev)), "wave_misfit")
+    return (J, r) if return_residual else J
 
 
 def tune_batch(shots, steps: int = 10):

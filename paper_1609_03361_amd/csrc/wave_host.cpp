@@ -43,30 +43,73 @@ int fail(int code, const char* fmt, ...)
                         __LINE__);                                                          \
     } while (0)
 
-// Optional per-thread phase timing (wave_set_profiling / wave_last_loop).
+// Per-thread state: phase timing (wave_set_profiling / wave_last_loop), the
+// pinned host staging buffer for the per-call uploads and the validation
+// read-back, the last instantiated batch graph with its capture stream, and
+// the mode of the last batched call.  Every thread's state is registered so
+// that wave_release can destroy the HIP objects of all of them (torch runs
+// the autograd backward on a thread of its own).  The small host structs are
+// never freed.
 struct Prof {
     bool on = false;
     bool have = false;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     int64_t launches = 0;
 };
-thread_local Prof g_prof;
+
+// Staging: grown on demand; an event marks the last use so that the buffer is
+// never rewritten while a copy reads it.
+struct Staging {
+    char* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+};
+
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    hipStream_t capture = nullptr;
+    std::vector<char> key;
+};
+
+struct ThreadState {
+    Prof prof;
+    Staging stage;
+    GraphCache graph;
+    // How the last batched call ran: 0 = per-step launches replayed from a
+    // hipGraph, 1 = per-step launches, 2 = one persistent launch, 3 = one
+    // persistent launch replayed from a hipGraph.
+    int batch_mode = -1;
+};
+
+std::mutex g_threads_mu;
+std::vector<ThreadState*> g_threads;
+
+ThreadState& TS()
+{
+    thread_local ThreadState* st = nullptr;
+    if (!st) {
+        st = new ThreadState;
+        std::lock_guard<std::mutex> lk(g_threads_mu);
+        g_threads.push_back(st);
+    }
+    return *st;
+}
 
 int prof_begin(hipStream_t s)
 {
-    g_prof.launches = 0;
-    g_prof.have = false;
-    if (!g_prof.on) return 0;
-    if (!g_prof.t0 && hipEventCreate(&g_prof.t0) != hipSuccess) return -1;
-    if (!g_prof.t1 && hipEventCreate(&g_prof.t1) != hipSuccess) return -1;
-    return hipEventRecord(g_prof.t0, s) == hipSuccess ? 0 : -1;
+    TS().prof.launches = 0;
+    TS().prof.have = false;
+    if (!TS().prof.on) return 0;
+    if (!TS().prof.t0 && hipEventCreate(&TS().prof.t0) != hipSuccess) return -1;
+    if (!TS().prof.t1 && hipEventCreate(&TS().prof.t1) != hipSuccess) return -1;
+    return hipEventRecord(TS().prof.t0, s) == hipSuccess ? 0 : -1;
 }
 
 int prof_end(hipStream_t s)
 {
-    if (!g_prof.on) return 0;
-    if (hipEventRecord(g_prof.t1, s) != hipSuccess) return -1;
-    g_prof.have = true;
+    if (!TS().prof.on) return 0;
+    if (hipEventRecord(TS().prof.t1, s) != hipSuccess) return -1;
+    TS().prof.have = true;
     return 0;
 }
 
@@ -315,6 +358,12 @@ size_t ckpt_bytes(const Geo& G, const wave_opts* o)
     return (size_t)nck * 2 * snap + round_up((size_t)nck * 4 * sizeof(float), kAlign);
 }
 
+// What each op keeps in its workspace.  Forward: coefficients, tables and the
+// wavefield pair.  Forward with checkpoints: the same plus the codec's
+// reduction scratch (the checkpoints themselves are the caller's).  Adjoint:
+// coefficients, tables and the adjoint pair.  Backward from checkpoints: the
+// replay ring, the adjoint pair and the gradient accumulator.  Gradient: all
+// of it, plus residual, modelled data and the checkpoint storage.
 Plan make_plan(int op, const Geo& G, int nsrc, int nrec, const wave_opts* o)
 {
     Plan P;
@@ -324,10 +373,12 @@ Plan make_plan(int op, const Geo& G, int nsrc, int nrec, const wave_opts* o)
     P.alpha = c.take(N * 4);
     P.beta = c.take(N * 4);
     P.check = c.take((size_t)kCheckBlocks * 3 * 4);
-    // sparse tables: the forward samples receivers and injects sources, the
-    // adjoint the other way round; the gradient needs both directions
-    const bool fwd = op != WAVE_OP_ADJOINT, adj = op != WAVE_OP_FORWARD;
-    const int npt[2] = {fwd ? nrec : 0, adj ? nsrc : 0};
+    // sparse tables: the forward (and the backward's replay) samples receivers
+    // and injects sources, the adjoint the other way round
+    const bool fwd = op != WAVE_OP_ADJOINT;
+    const bool adj = op == WAVE_OP_ADJOINT || op == WAVE_OP_GRADIENT || op == WAVE_OP_BACKWARD;
+    const bool samples_rec = fwd && op != WAVE_OP_BACKWARD;
+    const int npt[2] = {samples_rec ? nrec : 0, adj ? nsrc : 0};
     for (int s = 0; s < 2; ++s) {
         P.smp_base[s] = c.take((size_t)npt[s] * 8);
         P.smp_w[s] = c.take((size_t)npt[s] * nc * 4);
@@ -338,21 +389,29 @@ Plan make_plan(int op, const Geo& G, int nsrc, int nrec, const wave_opts* o)
         P.inj_ptr[s] = c.take(iuse[s] ? ((size_t)G.nrows() + 1) * 4 : 0);
         P.inj_ent[s] = c.take((size_t)ipt[s] * nc * sizeof(InjEntry));
     }
-    if (op == WAVE_OP_FORWARD || op == WAVE_OP_GRADIENT) {
+    if (op == WAVE_OP_FORWARD || op == WAVE_OP_FORWARD_CKPT || op == WAVE_OP_GRADIENT) {
         P.wf[0] = c.take(N * 4);
         P.wf[1] = c.take(N * 4);
     }
-    if (op == WAVE_OP_ADJOINT || op == WAVE_OP_GRADIENT) {
+    if (adj) {
         P.adj[0] = c.take(N * 4);
         P.adj[1] = c.take(N * 4);
     }
-    if (op == WAVE_OP_GRADIENT) {
+    if (op == WAVE_OP_GRADIENT || op == WAVE_OP_BACKWARD) {
         P.nring = std::min(ckpt_every(o), G.nt) + 1;
         P.ring = c.take(N * 4 * (size_t)P.nring);
         P.gacc = c.take(N * 4);
+    }
+    if (op == WAVE_OP_FORWARD && o && (o->flags & WAVE_FLAG_TUNE_IMAGING)) {
+        // wave_tune of the imaging step: a forward-field plane and a gradient
+        P.nring = 1;
+        P.ring = c.take(N * 4);
+        P.gacc = c.take(N * 4);
+    }
+    if (op == WAVE_OP_GRADIENT || op == WAVE_OP_FORWARD_CKPT) P.red = c.take(kRedFloats * 4);
+    if (op == WAVE_OP_GRADIENT) {
         P.resid = c.take((size_t)G.nt * nrec * 4);
         P.dsyn = c.take((size_t)G.nt * nrec * 4);
-        P.red = c.take(kRedFloats * 4);
         P.ckpt = c.take(ckpt_bytes(G, o));
     }
     P.total = c.off;
@@ -382,11 +441,16 @@ void tune_load_locked()
     std::fclose(f);
 }
 
-std::string tune_key(const Geo& G)
+// Everything a tile's timing depends on: dimension, order, shape, spacing
+// (through the weights, not the traffic, but kept apart to be safe) and
+// whether the launch is the adjoint step with the imaging condition, which
+// moves 32 instead of 20 bytes per point and holds more registers.
+std::string tune_key(const Geo& G, bool imaging)
 {
-    char b[128];
-    std::snprintf(b, sizeof b, "d%do%d:%lldx%lldx%lld", G.ndim, G.order, (long long)G.n[0],
-                  (long long)G.n[1], (long long)G.n[2]);
+    char b[192];
+    std::snprintf(b, sizeof b, "d%do%d:%lldx%lldx%lld:h%.9gx%.9gx%.9g%s", G.ndim, G.order,
+                  (long long)G.n[0], (long long)G.n[1], (long long)G.n[2], G.h[0], G.h[1], G.h[2],
+                  imaging ? ":img" : "");
     return b;
 }
 
@@ -445,6 +509,7 @@ struct Ctx {
     HostPoints rec, src;
     HostInject inj_src, inj_rec;
     TileCfg cfg;            // block shape and x-chunk of the streaming kernel
+    TileCfg cfg_img;        // the same for the adjoint step with the imaging condition
     template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
 
@@ -474,30 +539,19 @@ void set_weights(Ctx& C)
     }
 }
 
-// Pinned host staging for the per-call uploads (sparse tables) and the
-// validation read-back, one per thread, grown on demand.  An event marks the
-// last use so that a buffer is never rewritten while a copy reads it.  It is
-// deliberately not freed at thread exit (the runtime may already be gone).
-struct Staging {
-    char* host = nullptr;
-    size_t cap = 0;
-    hipEvent_t done = nullptr;
-};
-thread_local Staging g_stage;
-
 int staging(size_t bytes, char** out)
 {
-    if (g_stage.done) HIP_TRY(hipEventSynchronize(g_stage.done));
-    else HIP_TRY(hipEventCreateWithFlags(&g_stage.done, hipEventDisableTiming));
-    if (bytes > g_stage.cap) {
-        if (g_stage.host) HIP_TRY(hipHostFree(g_stage.host));
-        g_stage.host = nullptr;
-        g_stage.cap = 0;
+    if (TS().stage.done) HIP_TRY(hipEventSynchronize(TS().stage.done));
+    else HIP_TRY(hipEventCreateWithFlags(&TS().stage.done, hipEventDisableTiming));
+    if (bytes > TS().stage.cap) {
+        if (TS().stage.host) HIP_TRY(hipHostFree(TS().stage.host));
+        TS().stage.host = nullptr;
+        TS().stage.cap = 0;
         const size_t cap = round_up(std::max<size_t>(bytes, 1 << 20), 1 << 20);
-        HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&g_stage.host), cap, hipHostMallocDefault));
-        g_stage.cap = cap;
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&TS().stage.host), cap, hipHostMallocDefault));
+        TS().stage.cap = cap;
     }
-    *out = g_stage.host;
+    *out = TS().stage.host;
     return WAVE_OK;
 }
 
@@ -515,9 +569,11 @@ int setup(Ctx& C, int op, const wave_grid* grid, const float* m, const float* et
     if ((rc = check_ws(C.P, o))) return rc;
     C.ws = static_cast<char*>(o->workspace);
     C.s = static_cast<hipStream_t>(stream);
-    if ((rc = pick_tile(o, tune_key(C.G), C.G, &C.cfg))) return rc;
+    if ((rc = pick_tile(o, tune_key(C.G, false), C.G, &C.cfg))) return rc;
+    if ((rc = pick_tile(o, tune_key(C.G, true), C.G, &C.cfg_img))) return rc;
     set_weights(C);
-    const bool fwd = op != WAVE_OP_ADJOINT, adj = op != WAVE_OP_FORWARD;
+    const bool fwd = op != WAVE_OP_ADJOINT;
+    const bool adj = op == WAVE_OP_ADJOINT || op == WAVE_OP_GRADIENT || op == WAVE_OP_BACKWARD;
     if (fwd) make_inject(C.G, C.src, &C.inj_src);
     if (adj) make_inject(C.G, C.rec, &C.inj_rec);
 
@@ -525,7 +581,9 @@ int setup(Ctx& C, int op, const wave_grid* grid, const float* m, const float* et
     struct Up { size_t dst; const void* src; size_t bytes; };
     std::vector<Up> ups;
     const int nc = 1 << C.G.ndim;
-    const HostPoints* sp[2] = {fwd ? &C.rec : nullptr, adj ? &C.src : nullptr};
+    // the plan holds receiver sampling tables only for ops that sample them
+    const bool samples_rec = fwd && op != WAVE_OP_BACKWARD;
+    const HostPoints* sp[2] = {samples_rec ? &C.rec : nullptr, adj ? &C.src : nullptr};
     for (int s = 0; s < 2; ++s) {
         if (!sp[s] || sp[s]->npts == 0) continue;
         ups.push_back({C.P.smp_base[s], sp[s]->base.data(), (size_t)sp[s]->npts * 8});
@@ -554,7 +612,7 @@ int setup(Ctx& C, int op, const wave_grid* grid, const float* m, const float* et
                                 kCheckBlocks, C.at<float>(C.P.alpha), C.at<float>(C.P.beta),
                                 C.G.dt, C.s));
     HIP_TRY(hipMemcpyAsync(part, C.at<float>(C.P.check), part_bytes, hipMemcpyDeviceToHost, C.s));
-    HIP_TRY(hipEventRecord(g_stage.done, C.s));
+    HIP_TRY(hipEventRecord(TS().stage.done, C.s));
     HIP_TRY(hipStreamSynchronize(C.s));
     float mmin = INFINITY, bad = 0;
     for (int b = 0; b < kCheckBlocks; ++b) {
@@ -600,8 +658,8 @@ void bind_sparse(const Ctx& C, StepArgs& a, int set)
 
 hipError_t step(const Ctx& C, const StepArgs& a)
 {
-    ++g_prof.launches;
-    return launch_step(C.G.ndim, C.G.order, a, C.s, C.cfg);
+    ++TS().prof.launches;
+    return launch_step(C.G.ndim, C.G.order, a, C.s, a.img_grad ? C.cfg_img : C.cfg);
 }
 
 // Checkpoint storage: per checkpoint c two snapshot arrays (FP32: u^c and
@@ -706,7 +764,8 @@ int run_backward(const Ctx& C, const float* q, const float* r, const CkptView& c
     auto slot = [&](int i) { return ring + (size_t)i * N; };
     StepArgs fa = base_args(C);
     bind_sparse(C, fa, 0);
-    fa.smp_out = nullptr;
+    fa.smp_out = nullptr;       // the replay samples nothing (no receiver tables in this plan)
+    fa.smp.npts = 0;
     StepArgs ba = base_args(C);
     bind_sparse(C, ba, 1);
     ba.img_grad = gacc;
@@ -749,16 +808,18 @@ int run_backward(const Ctx& C, const float* q, const float* r, const CkptView& c
 // depend on the field values, and every candidate gives bitwise the same
 // result (the per-point arithmetic does not depend on the tiling).
 // ---------------------------------------------------------------------------
+// Candidate tiles: every block shape with x-chunks of 2R, 4R, 8 .. 128
+// planes, each clamped to what the shape accepts (the 2D slab holds at most
+// 16 rows) and to the grid, so that no two candidates launch the same thing.
 std::vector<TileCfg> tile_candidates(int ndim, int half, int64_t nx, int64_t nz)
 {
     std::vector<TileCfg> out;
     const int xs[] = {2 * half, 4 * half, 8, 16, 32, 64, 128};
     for (int v = 0; v < tile_variants(ndim, nz); ++v)
         for (int x : xs) {
-            if (x > nx && x != 2 * half) continue;
             TileCfg c;
             c.variant = v;
-            c.xchunk = (int)std::min<int64_t>(x, nx);
+            c.xchunk = (int)std::min<int64_t>(std::min(x, max_xchunk(ndim, v)), nx);
             bool dup = false;
             for (const TileCfg& o : out) dup = dup || (o.variant == c.variant && o.xchunk == c.xchunk);
             if (!dup) out.push_back(c);
@@ -862,16 +923,25 @@ StepArgs shot_args(const BatchShot& S, char* ws)
 }
 
 // Descriptors for a tile config; returns the total block count via *blocks.
+// The flattened block list takes the shots largest first (longest work
+// first: the last blocks of a launch, and the last items of each persistent
+// block, are then the small ones).  The order does not change any result:
+// each block computes one shot's tile, and shots are independent.
 void build_descs(const BatchPlan& B, const wave_shot* shots, char* ws, TileCfg cfg,
                  std::vector<ShotDesc>* desc, std::vector<int64_t>* begin, int64_t* blocks)
 {
     const int n = (int)B.shots.size();
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return B.shots[a].G.npad() > B.shots[b].G.npad(); });
     desc->assign(n, ShotDesc{});
     begin->assign(n + 1, 0);
     int64_t acc = 0;
-    for (int i = 0; i < n; ++i) {
+    for (int k = 0; k < n; ++k) {
+        const int i = order[k];
         const BatchShot& S = B.shots[i];
-        ShotDesc& D = (*desc)[i];
+        ShotDesc& D = (*desc)[k];
         D.a = shot_args(S, ws);
         D.a.smp_out = S.rec.npts ? shots[i].d : nullptr;   // marks sampling as active for planning
         const int64_t nb = plan_tiles(S.G.ndim, S.G.order, cfg, D.a);
@@ -882,7 +952,7 @@ void build_descs(const BatchPlan& B, const wave_shot* shots, char* ws, TileCfg c
         D.d = S.rec.npts ? shots[i].d : nullptr;
         D.nsrc = S.src.npts;
         D.nrec = S.rec.npts;
-        (*begin)[i] = acc;
+        (*begin)[k] = acc;
         acc += nb;
     }
     (*begin)[n] = acc;
@@ -930,7 +1000,7 @@ int batch_setup(const BatchPlan& B, const wave_shot* shots, char* ws, hipStream_
                                     reinterpret_cast<float*>(ws + S.beta), S.G.dt, st));
     }
     HIP_TRY(hipMemcpyAsync(part, ws + B.check, part_bytes, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipEventRecord(g_stage.done, st));
+    HIP_TRY(hipEventRecord(TS().stage.done, st));
     HIP_TRY(hipStreamSynchronize(st));
     for (int i = 0; i < n; ++i) {
         const BatchShot& S = B.shots[i];
@@ -963,7 +1033,7 @@ int upload_descs(const std::vector<ShotDesc>& desc, const std::vector<int64_t>& 
     std::memcpy(host + db, begin.data(), bb);
     HIP_TRY(hipMemcpyAsync(ws + B.desc, host, db, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(ws + B.begin, host + db, bb, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipEventRecord(g_stage.done, st));
+    HIP_TRY(hipEventRecord(TS().stage.done, st));
     return WAVE_OK;
 }
 
@@ -971,30 +1041,54 @@ std::string batch_key(const BatchPlan& B)
 {
     int64_t pts = 0, mx = 0;
     for (const BatchShot& S : B.shots) { pts += S.G.npts(); mx = std::max(mx, S.G.n[0]); }
-    char b[160];
+    char b[224];
     const Geo& G = B.shots[0].G;
-    std::snprintf(b, sizeof b, "batch:d%do%d:%zu:%lld:%lldx%lld", G.ndim, G.order, B.shots.size(),
-                  (long long)pts, (long long)mx, (long long)G.n[2]);
+    std::snprintf(b, sizeof b, "batch:d%do%d:%zu:%lld:%lldx%lld:h%.9gx%.9gx%.9g", G.ndim, G.order,
+                  B.shots.size(), (long long)pts, (long long)mx, (long long)G.n[2], G.h[0], G.h[1],
+                  G.h[2]);
     return b;
 }
 
-struct GraphCache {
-    hipGraphExec_t exec = nullptr;
-    hipStream_t capture = nullptr;
-    std::vector<char> key;
-};
-thread_local GraphCache g_graph;
+// Everything the instantiated graph bakes in.
+std::vector<char> graph_key(const ShotDesc* d_desc, const int64_t* d_begin, int64_t blocks,
+                            const Geo& G, int nshots, TileCfg cfg, int persistent)
+{
+    std::vector<char> key(sizeof(void*) * 2 + sizeof(int64_t) * 2 + sizeof(int) * 7);
+    char* k = key.data();
+    auto put = [&](const void* p, size_t n) { std::memcpy(k, p, n); k += n; };
+    put(&d_desc, sizeof(void*));
+    put(&d_begin, sizeof(void*));
+    put(&blocks, sizeof(int64_t));
+    const int64_t nz = G.nzp;
+    put(&nz, sizeof(int64_t));
+    const int v[7] = {nshots, G.nt, G.ndim, G.order, cfg.variant, cfg.xchunk, persistent};
+    put(v, sizeof v);
+    return key;
+}
 
+int instantiate_cached(hipGraph_t graph, const std::vector<char>& key)
+{
+    if (TS().graph.exec) {
+        HIP_TRY(hipGraphExecDestroy(TS().graph.exec));
+        TS().graph.exec = nullptr;
+        TS().graph.key.clear();
+    }
+    const hipError_t e = hipGraphInstantiate(&TS().graph.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        TS().graph.exec = nullptr;
+        return fail(WAVE_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    TS().graph.key = key;
+    return WAVE_OK;
+}
 
-// How the last batched call ran: 0 = per-step launches replayed from a
-// hipGraph, 1 = per-step launches, 2 = one persistent launch, 3 = one
-// persistent launch captured in a hipGraph.
-thread_local int g_batch_mode = -1;
-
-// One persistent cooperative launch for all steps, then a wait and a check of
-// the barrier error word, so a barrier that did not complete is reported,
-// never left hanging.
-int run_batch_persistent(const BatchPlan& B, char* ws, TileCfg cfg, int64_t items, hipStream_t st)
+// One persistent cooperative launch for all steps (directly, or as the
+// cooperative node of a cached graph), then a wait and a check of the
+// barrier error word, so a barrier that did not complete is reported, never
+// left hanging.
+int run_batch_persistent(const BatchPlan& B, char* ws, TileCfg cfg, int64_t items, hipStream_t st,
+                         bool use_graph)
 {
     const Geo& G = B.shots[0].G;
     const int nshots = (int)B.shots.size();
@@ -1002,25 +1096,32 @@ int run_batch_persistent(const BatchPlan& B, char* ws, TileCfg cfg, int64_t item
     const int64_t* d_begin = reinterpret_cast<const int64_t*>(ws + B.begin);
     unsigned int* sync = reinterpret_cast<unsigned int*>(ws + B.sync);
     const int32_t spin_limit = 2000000;   // a few seconds of polling per barrier at most
-    HIP_TRY(launch_fill(reinterpret_cast<float*>(sync), 2, 0.f, st));
     int grid = 0;
-    g_prof.launches += 1;
-    // a direct cooperative launch: the runtime refuses it unless every block
-    // can be resident at once, which the device-wide barrier relies on
-    int per_cu = 4;
-    if (const char* e = std::getenv("WAVE_PERSISTENT_BLOCKS_PER_CU")) per_cu = std::max(1, std::atoi(e));
-    HIP_TRY(launch_batch_persistent(G.ndim, G.order, G.nzp, cfg, d_desc, d_begin, nshots, items,
-                                    G.nt, sync, spin_limit, per_cu, &grid, st));
-    g_batch_mode = 2;
+    TS().prof.launches += 1;
+    if (!use_graph) {
+        HIP_TRY(launch_fill(reinterpret_cast<float*>(sync), 2, 0.f, st));
+        HIP_TRY(launch_batch_persistent(G.ndim, G.order, G.nzp, cfg, d_desc, d_begin, nshots, items,
+                                        G.nt, sync, spin_limit, &grid, st));
+        TS().batch_mode = 2;
+    } else {
+        const std::vector<char> key = graph_key(d_desc, d_begin, items, G, nshots, cfg, 1);
+        if (!TS().graph.exec || TS().graph.key != key) {
+            hipGraph_t graph = nullptr;
+            HIP_TRY(graph_batch_persistent(G.ndim, G.order, G.nzp, cfg, d_desc, d_begin, nshots,
+                                           items, G.nt, sync, spin_limit, &grid, &graph));
+            const int rc = instantiate_cached(graph, key);
+            if (rc) return rc;
+        }
+        HIP_TRY(hipGraphLaunch(TS().graph.exec, st));
+        TS().batch_mode = 3;
+    }
     unsigned int words[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(words, sync, sizeof words, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (words[1])
-        return fail(WAVE_EHIP, "persistent batch: a device-wide barrier timed out (grid %d blocks)", grid);
+        return fail(WAVE_EHIP, "persistent batch: a device-wide barrier timed out");
     return WAVE_OK;
 }
-
-
 
 int run_batch_loop(const BatchPlan& B, char* ws, TileCfg cfg, int64_t blocks, hipStream_t st,
                    bool use_graph)
@@ -1029,49 +1130,34 @@ int run_batch_loop(const BatchPlan& B, char* ws, TileCfg cfg, int64_t blocks, hi
     const int nshots = (int)B.shots.size();
     const ShotDesc* d_desc = reinterpret_cast<const ShotDesc*>(ws + B.desc);
     const int64_t* d_begin = reinterpret_cast<const int64_t*>(ws + B.begin);
-    g_batch_mode = use_graph ? 0 : 1;
+    TS().batch_mode = use_graph ? 0 : 1;
     if (!use_graph) {
         for (int n = 0; n < G.nt; ++n) {
-            ++g_prof.launches;
+            ++TS().prof.launches;
             HIP_TRY(launch_batch(G.ndim, G.order, G.nzp, cfg, d_desc, d_begin, nshots, blocks, n, st));
         }
         return WAVE_OK;
     }
-    // graph identity: everything the captured launches bake in
-    std::vector<char> key(sizeof(void*) * 2 + sizeof(int64_t) * 2 + sizeof(int) * 6);
-    {
-        char* k = key.data();
-        auto put = [&](const void* p, size_t n) { std::memcpy(k, p, n); k += n; };
-        put(&d_desc, sizeof(void*)); put(&d_begin, sizeof(void*));
-        put(&blocks, sizeof(int64_t)); int64_t nz = G.nzp; put(&nz, sizeof(int64_t));
-        int v[6] = {nshots, G.nt, G.ndim, G.order, cfg.variant, cfg.xchunk};
-        put(v, sizeof v);
-    }
-    if (!g_graph.exec || g_graph.key != key) {
-        if (g_graph.exec) { HIP_TRY(hipGraphExecDestroy(g_graph.exec)); g_graph.exec = nullptr; }
-        if (!g_graph.capture) HIP_TRY(hipStreamCreateWithFlags(&g_graph.capture, hipStreamNonBlocking));
-        HIP_TRY(hipStreamBeginCapture(g_graph.capture, hipStreamCaptureModeThreadLocal));
+    const std::vector<char> key = graph_key(d_desc, d_begin, blocks, G, nshots, cfg, 0);
+    if (!TS().graph.exec || TS().graph.key != key) {
+        if (!TS().graph.capture) HIP_TRY(hipStreamCreateWithFlags(&TS().graph.capture, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(TS().graph.capture, hipStreamCaptureModeThreadLocal));
         hipError_t err = hipSuccess;
         for (int n = 0; n < G.nt && err == hipSuccess; ++n)
             err = launch_batch(G.ndim, G.order, G.nzp, cfg, d_desc, d_begin, nshots, blocks, n,
-                               g_graph.capture);
+                               TS().graph.capture);
         hipGraph_t graph = nullptr;
-        const hipError_t e2 = hipStreamEndCapture(g_graph.capture, &graph);
+        const hipError_t e2 = hipStreamEndCapture(TS().graph.capture, &graph);
         if (err != hipSuccess || e2 != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
             return fail(WAVE_EHIP, "graph capture of the batched loop failed: %s",
                         hipGetErrorString(err != hipSuccess ? err : e2));
         }
-        const hipError_t e3 = hipGraphInstantiate(&g_graph.exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (e3 != hipSuccess) {
-            g_graph.exec = nullptr;
-            return fail(WAVE_EHIP, "graph instantiation failed: %s", hipGetErrorString(e3));
-        }
-        g_graph.key = key;
+        const int rc = instantiate_cached(graph, key);
+        if (rc) return rc;
     }
-    g_prof.launches += G.nt;
-    HIP_TRY(hipGraphLaunch(g_graph.exec, st));
+    TS().prof.launches += G.nt;
+    HIP_TRY(hipGraphLaunch(TS().graph.exec, st));
     return WAVE_OK;
 }
 
@@ -1083,24 +1169,113 @@ const char* wave_last_error(void) { return g_error.c_str(); }
 
 const char* wave_version(void) { return "wavefd-mi355x 0.1 (gfx950)"; }
 
-int wave_last_batch_mode(void) { return g_batch_mode; }
+int wave_last_batch_mode(void) { return TS().batch_mode; }
+
+int wave_release(void)
+{
+    // Per thread, in dependency order: the graph executable, its capture
+    // stream, the timing events, then the pinned staging buffer after its
+    // last copy.
+    int rc = WAVE_OK;
+    auto note = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && rc == WAVE_OK)
+            rc = fail(WAVE_EHIP, "wave_release: %s: %s", what, hipGetErrorString(e));
+    };
+    std::lock_guard<std::mutex> lk(g_threads_mu);
+    for (ThreadState* t : g_threads) {
+        if (t->graph.exec) note(hipGraphExecDestroy(t->graph.exec), "hipGraphExecDestroy");
+        t->graph.exec = nullptr;
+        t->graph.key.clear();
+        if (t->graph.capture) note(hipStreamDestroy(t->graph.capture), "hipStreamDestroy");
+        t->graph.capture = nullptr;
+        if (t->prof.t0) note(hipEventDestroy(t->prof.t0), "hipEventDestroy");
+        if (t->prof.t1) note(hipEventDestroy(t->prof.t1), "hipEventDestroy");
+        t->prof.t0 = t->prof.t1 = nullptr;
+        t->prof.have = false;
+        if (t->stage.done) {
+            note(hipEventSynchronize(t->stage.done), "hipEventSynchronize");
+            note(hipEventDestroy(t->stage.done), "hipEventDestroy");
+        }
+        t->stage.done = nullptr;
+        if (t->stage.host) note(hipHostFree(t->stage.host), "hipHostFree");
+        t->stage.host = nullptr;
+        t->stage.cap = 0;
+    }
+    return rc;
+}
+
+int wave_tile_candidates(const wave_grid* grid, int32_t* ids, int32_t cap, int32_t* n)
+{
+    try {
+        if (!n || cap < 0 || (cap > 0 && !ids)) return fail(WAVE_EINVAL, "n is required, ids for cap > 0");
+        Geo G;
+        int rc = make_geo(grid, &G);
+        if (rc) return rc;
+        const std::vector<TileCfg> c = tile_candidates(G.ndim, G.half, G.n[0], G.nzp);
+        *n = (int32_t)c.size();
+        for (int32_t i = 0; i < cap && i < (int32_t)c.size(); ++i) ids[i] = tile_id(c[i]);
+        return WAVE_OK;
+    } catch (const std::exception& e) {
+        return fail(WAVE_EINVAL, "exception: %s", e.what());
+    }
+}
+
+int wave_resolve_tile(const wave_grid* grid, int32_t tile, int32_t* resolved)
+{
+    try {
+        if (!resolved) return fail(WAVE_EINVAL, "resolved is NULL");
+        Geo G;
+        int rc = make_geo(grid, &G);
+        if (rc) return rc;
+        wave_opts o;
+        std::memset(&o, 0, sizeof o);
+        o.tile = tile;
+        TileCfg cfg;
+        if ((rc = pick_tile(&o, tune_key(G, false), G, &cfg))) return rc;
+        StepArgs a;
+        std::memset(&a, 0, sizeof a);
+        a.nx = G.n[0]; a.ny = G.n[1]; a.nz = G.nzp;
+        if (plan_tiles(G.ndim, G.order, cfg, a) < 0) return fail(WAVE_EINVAL, "tile %d cannot be planned", tile);
+        TileCfg out = cfg;
+        out.xchunk = a.xchunk;
+        *resolved = tile_id(out);
+        return WAVE_OK;
+    } catch (const std::exception& e) {
+        return fail(WAVE_EINVAL, "exception: %s", e.what());
+    }
+}
+
+int wave_misfit(const float* d, const float* d_obs, int64_t n, float* r, float* misfit,
+                const wave_opts* opts, void* stream)
+{
+    if (!misfit || n < 0 || (n > 0 && (!d || !d_obs)))
+        return fail(WAVE_EINVAL, "misfit is required, n >= 0, and d and d_obs when n > 0");
+    if (!opts || !opts->workspace || reinterpret_cast<uintptr_t>(opts->workspace) % kAlign)
+        return fail(WAVE_EWORKSPACE, "workspace missing or not %zu-byte aligned", kAlign);
+    if (opts->workspace_bytes < (size_t)WAVE_MISFIT_WORKSPACE_BYTES)
+        return fail(WAVE_EWORKSPACE, "workspace too small: %zu bytes given, %d needed",
+                    opts->workspace_bytes, WAVE_MISFIT_WORKSPACE_BYTES);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(launch_residual(d, d_obs, r, n, static_cast<float*>(opts->workspace), kRedFloats, misfit, st));
+    return WAVE_OK;
+}
 
 int wave_set_profiling(int32_t enable)
 {
-    g_prof.on = enable != 0;
-    g_prof.have = false;
+    TS().prof.on = enable != 0;
+    TS().prof.have = false;
     return WAVE_OK;
 }
 
 int wave_last_loop(double* ms, int64_t* launches)
 {
     if (!ms || !launches) return fail(WAVE_EINVAL, "ms and launches are required");
-    if (!g_prof.have) return fail(WAVE_EINVAL, "no profiled call on this thread");
-    HIP_TRY(hipEventSynchronize(g_prof.t1));
+    if (!TS().prof.have) return fail(WAVE_EINVAL, "no profiled call on this thread");
+    HIP_TRY(hipEventSynchronize(TS().prof.t1));
     float f = 0.f;
-    HIP_TRY(hipEventElapsedTime(&f, g_prof.t0, g_prof.t1));
+    HIP_TRY(hipEventElapsedTime(&f, TS().prof.t0, TS().prof.t1));
     *ms = f;
-    *launches = g_prof.launches;
+    *launches = TS().prof.launches;
     return WAVE_OK;
 }
 
@@ -1109,7 +1284,7 @@ int wave_workspace_size(int32_t op, const wave_grid* grid, const wave_points* sr
 {
     try {
         if (!bytes) return fail(WAVE_EINVAL, "bytes is NULL");
-        if (op < WAVE_OP_FORWARD || op > WAVE_OP_GRADIENT) return fail(WAVE_EINVAL, "unknown op %d", op);
+        if (op < WAVE_OP_FORWARD || op > WAVE_OP_BACKWARD) return fail(WAVE_EINVAL, "unknown op %d", op);
         Geo G;
         int rc = make_geo(grid, &G);
         if (rc) return rc;
@@ -1142,7 +1317,7 @@ int wave_forward(const wave_grid* grid, const float* m, const float* eta, const 
 {
     try {
         Ctx C;
-        const int op = ckpt ? WAVE_OP_GRADIENT : WAVE_OP_FORWARD;
+        const int op = ckpt ? WAVE_OP_FORWARD_CKPT : WAVE_OP_FORWARD;
         if (src && src->npts > 0 && !q) return fail(WAVE_EINVAL, "q is NULL with %d sources", src->npts);
         if (rec && rec->npts > 0 && !d) return fail(WAVE_EINVAL, "d is NULL with %d receivers", rec->npts);
         int rc = setup(C, op, grid, m, eta, src, rec, opts, stream);
@@ -1206,7 +1381,7 @@ int wave_backward(const wave_grid* grid, const float* m, const float* eta, const
         if (!grad_m) return fail(WAVE_EINVAL, "grad_m is NULL");
         if (src && src->npts > 0 && !q) return fail(WAVE_EINVAL, "q is NULL with %d sources", src->npts);
         if (rec && rec->npts > 0 && !r) return fail(WAVE_EINVAL, "r is NULL with %d receivers", rec->npts);
-        int rc = setup(C, WAVE_OP_GRADIENT, grid, m, eta, src, rec, opts, stream);
+        int rc = setup(C, WAVE_OP_BACKWARD, grid, m, eta, src, rec, opts, stream);
         if (rc) return rc;
         CkptView ck = ckpt_view(C.G, opts, const_cast<void*>(ckpt));
         return run_backward(C, q, r, ck, grad_m, grad_q, true);
@@ -1285,7 +1460,7 @@ int wave_forward_batch(int32_t nshots, const wave_shot* shots, const wave_opts* 
         if ((rc = upload_descs(desc, begin, ws, B, st))) return rc;
         if (prof_begin(st)) return fail(WAVE_EHIP, "profiling event failed");
         if (opts->flags & WAVE_FLAG_PERSISTENT)
-            rc = run_batch_persistent(B, ws, cfg, blocks, st);
+            rc = run_batch_persistent(B, ws, cfg, blocks, st, !(opts->flags & WAVE_FLAG_NO_GRAPH));
         else
             rc = run_batch_loop(B, ws, cfg, blocks, st, !(opts->flags & WAVE_FLAG_NO_GRAPH));
         if (rc) return rc;
@@ -1315,6 +1490,7 @@ int wave_tune(const wave_grid* grid, const wave_opts* opts, int32_t steps, void*
         if (rc) return rc;
         C.P = make_plan(WAVE_OP_FORWARD, C.G, 0, 0, opts);
         if ((rc = check_ws(C.P, opts))) return rc;
+        const bool imaging = (opts->flags & WAVE_FLAG_TUNE_IMAGING) != 0;
         C.ws = static_cast<char*>(opts->workspace);
         C.s = static_cast<hipStream_t>(stream);
         set_weights(C);
@@ -1324,6 +1500,12 @@ int wave_tune(const wave_grid* grid, const wave_opts* opts, int32_t steps, void*
         StepArgs a = base_args(C);
         a.cur = C.at<float>(C.P.wf[0]);
         a.other = a.out = C.at<float>(C.P.wf[1]);
+        if (imaging) {
+            HIP_TRY(launch_fill(C.at<float>(C.P.ring), N, 0.f, C.s));
+            HIP_TRY(launch_fill(C.at<float>(C.P.gacc), N, 0.f, C.s));
+            a.img_fwd = C.at<float>(C.P.ring);
+            a.img_grad = C.at<float>(C.P.gacc);
+        }
         EventPair ev;
         HIP_TRY(hipEventCreate(&ev.a));
         HIP_TRY(hipEventCreate(&ev.b));
@@ -1345,7 +1527,7 @@ int wave_tune(const wave_grid* grid, const wave_opts* opts, int32_t steps, void*
         }
         *tile = tile_id(best_cfg);
         *us_per_step = best;
-        store_tile(tune_key(C.G), *tile);
+        store_tile(tune_key(C.G, imaging), *tile);
         return WAVE_OK;
     } catch (const std::exception& e) {
         return fail(WAVE_EINVAL, "exception: %s", e.what());
@@ -1424,7 +1606,7 @@ int wave_diffusion(const wave_grid* grid, const float* a, const float* u0, float
         if ((rc = check_ws(C.P, opts))) return rc;
         C.ws = static_cast<char*>(opts->workspace);
         C.s = static_cast<hipStream_t>(stream);
-        if ((rc = pick_tile(opts, tune_key(C.G), C.G, &C.cfg))) return rc;
+        if ((rc = pick_tile(opts, tune_key(C.G, false), C.G, &C.cfg))) return rc;
         set_weights(C);
         const int64_t N = C.G.npad();
         char* host = nullptr;
@@ -1435,7 +1617,7 @@ int wave_diffusion(const wave_grid* grid, const float* a, const float* u0, float
                                       C.G.dt, C.s));
         HIP_TRY(hipMemcpyAsync(part, C.at<float>(C.P.check), (size_t)kCheckBlocks * 2 * 4,
                                hipMemcpyDeviceToHost, C.s));
-        HIP_TRY(hipEventRecord(g_stage.done, C.s));
+        HIP_TRY(hipEventRecord(TS().stage.done, C.s));
         HIP_TRY(hipStreamSynchronize(C.s));
         float amax = 0.f, bad = 0.f;
         for (int b = 0; b < kCheckBlocks; ++b) {
@@ -1459,10 +1641,11 @@ int wave_diffusion(const wave_grid* grid, const float* a, const float* u0, float
         HIP_TRY(copy_in(buf[0], u0, C.G, C.s));
         HIP_TRY(launch_fill(buf[1], N, 0.f, C.s));
         StepArgs sa = base_args(C);
+        sa.no_prev = 1;                      // beta = 0: neither u^{n-1} nor beta is read
         if (prof_begin(C.s)) return fail(WAVE_EHIP, "profiling event failed");
         for (int n = 0; n < C.G.nt; ++n) {
             sa.cur = buf[n & 1];
-            sa.other = buf[(n + 1) & 1];     // multiplied by beta = 0; finite by construction
+            sa.other = buf[(n + 1) & 1];
             sa.out = buf[(n + 1) & 1];
             HIP_TRY(step(C, sa));
         }

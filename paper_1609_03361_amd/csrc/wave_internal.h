@@ -60,6 +60,10 @@ struct StepArgs {
     const float* img_fwd;  // u^k, or nullptr
     float* img_grad;
     float inv_dt2;
+    // 1 when beta is zero everywhere (forward-Euler diffusion): the step then
+    // reads neither `other` nor beta (12 instead of 20 bytes per update); the
+    // update is unchanged, since beta (cur - other) is then zero
+    int32_t no_prev;
 };
 
 // One shot of a batched launch: the static step arguments plus the base
@@ -81,9 +85,54 @@ struct TileCfg {
 inline TileCfg tile_from_id(int id) { TileCfg c; c.variant = (id >> 16) & 0xff; c.xchunk = id & 0xffff; return c; }
 inline int tile_id(const TileCfg& c) { return (c.variant << 16) | c.xchunk; }
 
-// Number of block-shape variants for a grid (2D: 3, 3D: 6; the row length
+// Rows of u^n a 2D slab block computes at most (its x-chunk); the LDS slab
+// holds them with R halo rows on either side.
+constexpr int kSlabRows = 16;
+
+// Block shapes of the step kernel: z-points per lane, lanes along z and rows
+// along y (2D: rows along x, computed by the slab body when > 1).
+//   2D: one wave with four z-points per lane (256 z), 128 scalar lanes
+//   (128 z), one wave with two z-points per lane (128 z), or the slab body
+//   with eight waves of four-point lanes (256 z, chunks of up to 16 rows held
+//   in LDS, two rows per wave; measured against four waves with four rows
+//   each: 167 us against 170 us on the 48 batched shots, and 172 us for the
+//   streaming body).
+//   3D, four z-points per lane: 64 z x 16 rows, 64 z x 8 rows, 32 z x 32
+//   rows, 100 z x 10 rows or 200 z x 5 rows (the last two cover grids such as
+//   200^3 without a mostly empty last tile); two z-points per lane: 64 z x 8
+//   rows (half the queue registers per lane).
+struct BlockShape {
+    int vz, tzl, ty;
+};
+constexpr BlockShape kShapes2D[] = {{4, 64, 1}, {1, 128, 1}, {2, 64, 1}, {4, 64, 8}};
+constexpr BlockShape kShapes3D[] = {{4, 16, 16}, {4, 16, 8}, {4, 8, 32}, {4, 25, 10}, {4, 50, 5}, {2, 32, 8}};
+
+// The step kernels of one space order O (defined in wave_step.h, instantiated
+// in wave_o<O>.hip); the launch_* functions below dispatch to them.
+template <int O>
+struct OrderOps {
+    static int64_t plan(int ndim, TileCfg cfg, StepArgs& a);
+    static hipError_t step(int ndim, const StepArgs& a, hipStream_t s, TileCfg cfg);
+    static hipError_t batch(int ndim, int64_t nz_any, TileCfg cfg, const ShotDesc* shots,
+                            const int64_t* begin, int32_t nshots, int64_t blocks, int32_t n,
+                            hipStream_t s);
+    static hipError_t persistent(int ndim, int64_t nz_any, TileCfg cfg, const ShotDesc* shots,
+                                 const int64_t* begin, int32_t nshots, int64_t items, int32_t nt,
+                                 unsigned int* sync, int32_t spin_limit, int* grid_used,
+                                 hipStream_t s);
+    static hipError_t persistent_graph(int ndim, int64_t nz_any, TileCfg cfg,
+                                       const ShotDesc* shots, const int64_t* begin,
+                                       int32_t nshots, int64_t items, int32_t nt,
+                                       unsigned int* sync, int32_t spin_limit, int* grid_used,
+                                       hipGraph_t* graph);
+};
+
+// Number of block-shape variants for a grid (2D: 4, 3D: 6; the row length
 // handed to the kernels is always a multiple of 4).
 int tile_variants(int ndim, int64_t nz);
+// Longest x-chunk a block shape accepts (the 2D slab holds at most 16 rows;
+// the streaming shapes have no limit below the grid).
+int max_xchunk(int ndim, int variant);
 // Block shape used when no tile is given or cached: in 2D the slab body; in
 // 3D the one whose tiles waste the fewest lanes on the (ny, nz) plane, ties
 // broken by a measured preference order that depends on the space order.
@@ -102,12 +151,22 @@ hipError_t launch_batch(int ndim, int order, int64_t nz_any, TileCfg cfg, const 
 // All nt steps of all shots in one cooperative (co-resident) launch with a
 // device-wide barrier per step.  `sync` = {arrival counter, error word}, both
 // zero at launch; the error word is set if a barrier wait exceeded
-// `spin_limit` polls.  At most max_per_cu blocks per CU are launched;
-// *grid_used receives the number of blocks.
+// `spin_limit` polls.  The grid is as many blocks as the kernel's occupancy
+// lets every CU hold at once (never more than `items`); the cooperative
+// launch is refused rather than run with fewer resident.  *grid_used
+// receives the number of blocks.
 hipError_t launch_batch_persistent(int ndim, int order, int64_t nz_any, TileCfg cfg,
                                    const ShotDesc* shots, const int64_t* begin, int32_t nshots,
                                    int64_t items, int32_t nt, unsigned int* sync, int32_t spin_limit,
-                                   int max_per_cu, int* grid_used, hipStream_t s);
+                                   int* grid_used, hipStream_t s);
+// The same persistent kernel as a graph: a kernel node that zeroes `sync`
+// followed by the persistent kernel as a node with the cooperative launch
+// attribute (co-resident grid, sized by the kernel's occupancy).  *graph is
+// created here and owned by the caller.
+hipError_t graph_batch_persistent(int ndim, int order, int64_t nz_any, TileCfg cfg,
+                                  const ShotDesc* shots, const int64_t* begin, int32_t nshots,
+                                  int64_t items, int32_t nt, unsigned int* sync, int32_t spin_limit,
+                                  int* grid_used, hipGraph_t* graph);
 // One pass over the model: per block {min m, min eta, count of invalid values}
 // into `partial` (3 * nblocks floats) for the host-side validation, and the
 // step coefficients alpha = dt^2/(m + eta dt/2), beta = (m - eta dt/2)/(m + eta dt/2).

@@ -1,0 +1,5 @@
+// Step kernels of space order 14 (half-width 7): every block shape, plain
+// and imaging steps, the batch kernel and the persistent kernel.
+#include "wave_step.h"
+
+template struct wave::OrderOps<14>;

@@ -37,11 +37,12 @@ class FWIState:
 
 
 def misfit(state: FWIState, m: torch.Tensor) -> float:
-    """J(m) = 1/2 sum over shots of |d(m) - d_obs|^2 (forward runs only)."""
+    """J(m) = 1/2 sum over shots of |d(m) - d_obs|^2 (forward runs and the
+    library's misfit reduction only)."""
     J = 0.0
     for geom, q, d_obs in state.shots:
         d = api.forward(geom, m, state.eta, q)
-        J += 0.5 * float(((d - d_obs).double() ** 2).sum())
+        J += float(api.misfit(d, d_obs))
     return J
 
 

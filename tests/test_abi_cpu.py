@@ -152,3 +152,47 @@ def test_batch_rejects_mismatched_shots_before_device_work():
     assert b"same ndim" in L.lib().wave_last_error()
     arr[1].grid = L.make_grid((25, 30), (10.0, 10.0), 8, 1e-3, 10)
     assert L.lib().wave_batch_workspace_size(2, arr, None, C.byref(n)) == 0 and n.value > 0
+
+
+def test_workspace_of_each_op_holds_only_what_it_touches():
+    rec = np.zeros((50, 2))
+    src = np.zeros((2, 2))
+    sizes = {op: _size(op, src=src, rec=rec, nt=100)[1]
+             for op in (L.WAVE_OP_FORWARD, L.WAVE_OP_ADJOINT, L.WAVE_OP_GRADIENT,
+                        L.WAVE_OP_FORWARD_CKPT, L.WAVE_OP_BACKWARD)}
+    # forward with caller-owned checkpoints: the forward plus 4 KiB of reduction
+    # scratch (the codec's maxima), no ring, no adjoint fields
+    assert sizes[L.WAVE_OP_FORWARD] < sizes[L.WAVE_OP_FORWARD_CKPT] <= sizes[L.WAVE_OP_FORWARD] + 4096 + 256
+    # backward: ring of ckpt_every + 1 fields, adjoint pair and accumulator, no checkpoints
+    assert sizes[L.WAVE_OP_BACKWARD] < sizes[L.WAVE_OP_GRADIENT]
+    rc, ck = 0, C.c_size_t(0)
+    g = L.make_grid((20, 30), (10.0, 10.0), 8, 1e-3, 100)
+    assert L.lib().wave_checkpoint_size(C.byref(g), C.byref(L.make_opts()), C.byref(ck)) == 0
+    assert sizes[L.WAVE_OP_GRADIENT] >= sizes[L.WAVE_OP_BACKWARD] + ck.value
+    rc, bad = _size(5)
+    assert rc == L.WAVE_EINVAL
+
+
+@pytest.mark.parametrize("shape", [(2001, 801), (101, 101), (5, 9), (256, 256, 256), (48, 48, 48)])
+@pytest.mark.parametrize("order", [4, 8, 16])
+def test_tile_candidates_are_distinct_launches(shape, order):
+    from paper_1609_03361_amd import api
+    geom = api.Geometry(shape, (10.0,) * len(shape), order, 1e-3, 10)
+    ids = api.tile_candidates(geom)
+    assert len(ids) == len(set(ids)) > 0
+    for t in ids:
+        variant, xc = t >> 16, t & 0xFFFF
+        assert 1 <= xc <= shape[0]
+        if len(shape) == 2 and variant == 3:
+            assert xc <= 16                  # the slab holds at most 16 rows
+        # the tile the launch uses is the candidate itself
+        assert api.resolve_tile(geom, t) == t
+
+
+def test_resolve_tile_clamps_requests():
+    from paper_1609_03361_amd import api
+    geom = api.Geometry((2001, 801), (10.0, 10.0), 8, 1e-3, 10)
+    assert api.resolve_tile(geom, (3 << 16) | 64) == (3 << 16) | 16
+    assert api.resolve_tile(geom, (0 << 16) | 5000) == (0 << 16) | 2001
+    with pytest.raises(L.WaveError):
+        api.resolve_tile(geom, 9 << 16)

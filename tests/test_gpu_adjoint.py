@@ -147,3 +147,24 @@ def test_reduced_precision_checkpoints_on_padded_rows(dev, dtype, tol):
     assert e < tol
     assert e32 < 1e-4
     assert float(Jr) == float(J32)      # the misfit comes from the forward run only
+
+
+def test_misfit_entry_point(dev):
+    """wave_misfit: J = 1/2 |d - d_obs|^2 and r = d - d_obs, equal to the
+    misfit that wave_gradient reports for the same data, and within FP32
+    summation error of the FP64 sum."""
+    import torch
+    from paper_1609_03361_amd import api
+    p, d_obs = _gradient_case((44, 40), 8, 90)
+    geom, m, eta, q = device_inputs(p, dev)
+    do = torch.from_numpy(d_obs).to(dev)
+    d = api.forward(geom, m, eta, q)
+    J, r = api.misfit(d, do, return_residual=True)
+    Jg, g = api.gradient(geom, m, eta, q, do)
+    torch.cuda.synchronize()
+    assert torch.equal(r, d - do)
+    assert float(J) == float(Jg)
+    ref = 0.5 * float(((d.double() - do.double()) ** 2).sum())
+    # FP32 partial sums over n = 90 * 17 terms: relative error below n * 2^-24
+    assert abs(float(J) - ref) <= d.numel() * 6e-8 * ref
+    assert float(api.misfit(d[:0], do[:0])) == 0.0

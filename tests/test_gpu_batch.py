@@ -115,17 +115,56 @@ def test_tuner_picks_a_tile_and_results_stay_bitwise(dev):
     assert bt > 0
 
 
-def test_persistent_batch_equals_per_step_batch_bitwise(dev):
+@pytest.mark.parametrize("graph", [True, False])
+def test_persistent_batch_equals_per_step_batch_bitwise(dev, graph):
     """All steps of all shots in one persistent co-resident launch with a
-    device-wide barrier per step: bitwise the per-step result."""
+    device-wide barrier per step, as the cooperative node of a hipGraph (mode
+    3) or launched directly (mode 2): bitwise the per-step result, also when
+    the graph is replayed a second time."""
     import torch
     from paper_1609_03361_amd import api
     probs, shots = _shots(dev, n=5, nt=90)
     a = api.forward_batch(shots, return_final=True)
-    b = api.forward_batch(shots, return_final=True, persistent=True)
-    mode = api.last_batch_mode()
+    for rep in range(2):
+        print(f"persistent batch, graph={graph}, call {rep}", flush=True)
+        b = api.forward_batch(shots, return_final=True, persistent=True, graph=graph)
+        mode = api.last_batch_mode()
+        torch.cuda.synchronize()
+        print(f"persistent batch ran in mode {mode}", flush=True)
+        assert mode == (3 if graph else 2)
+        for x, y in zip(a[0] + a[1], b[0] + b[1]):
+            assert torch.equal(x, y)
+
+
+def test_persistent_3d_batch_equals_single(dev):
+    import torch
+    from paper_1609_03361_amd import api
+    shots = []
+    for k, shape in enumerate([(20, 18, 24), (31, 22, 24), (17, 26, 24)]):
+        p = synth.random_problem(shape, 8, 30, seed=40 + k, nsrc=2, nrec=6)
+        p.dt = 0.0004
+        shots.append(device_inputs(p, dev))
+    d, u = api.forward_batch(shots, return_final=True, persistent=True)
+    for i, (geom, m, eta, q) in enumerate(shots):
+        ds, us = api.forward(geom, m, eta, q, return_final=True)
+        torch.cuda.synchronize()
+        assert torch.equal(ds, d[i]) and torch.equal(us, u[i])
+
+
+def test_imaging_tile_tuned_separately_and_gradient_unchanged(dev):
+    """wave_tune with the imaging flag times the adjoint step with the fused
+    imaging condition; its winner is cached under its own key, and the
+    gradient does not change by a bit."""
+    import torch
+    from paper_1609_03361_amd import api
+    p = synth.random_problem((30, 28, 36), 8, 40, seed=8, nsrc=2, nrec=9)
+    geom, m, eta, q = device_inputs(p, dev)
+    d_obs = api.forward(geom, m * 1.01, eta, q)
+    J0, g0 = api.gradient(geom, m, eta, q, d_obs, ckpt_every=10)
+    t_img, us_img = api.tune(geom, steps=3, imaging=True)
+    t_fwd, us_fwd = api.tune(geom, steps=3)
+    print(f"imaging tile {t_img >> 16}/{t_img & 0xffff} {us_img:.2f} us; "
+          f"plain tile {t_fwd >> 16}/{t_fwd & 0xffff} {us_fwd:.2f} us", flush=True)
+    J1, g1 = api.gradient(geom, m, eta, q, d_obs, ckpt_every=10)
     torch.cuda.synchronize()
-    print(f"persistent batch ran in mode {mode}", flush=True)
-    assert mode == 2
-    for x, y in zip(a[0] + a[1], b[0] + b[1]):
-        assert torch.equal(x, y)
+    assert torch.equal(g0, g1) and torch.equal(J0, J1)

@@ -148,6 +148,26 @@ int wave_forward(const wave_grid* grid, const float* m, const float* eta,
                  float* u_final, void* ckpt, const wave_opts* opts, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under hipGraph stream
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * forward modelling as wave_forward without checkpoints and with the tuned or
+ * default tile, bitwise the same results, but the workspace is a device array
+ * of WAVE_NOALLOC_WORKSPACE_BYTES that the library holds on every device it
+ * runs on until the process ends.  The call makes no device allocation and
+ * pins no host memory (no hipMalloc, hipHostMalloc or hipFree; its host-side
+ * tables use ordinary heap memory).  A grid and point set whose forward
+ * workspace (wave_workspace_size, op WAVE_OP_FORWARD) exceeds that size is
+ * rejected with WAVE_EWORKSPACE before anything runs.  Every call on one
+ * device uses the same array: calls on one device must be ordered on one
+ * stream (or synchronised); overlapping calls race.  Each call initialises
+ * everything it reads from the array.
+ */
+#define WAVE_NOALLOC_WORKSPACE_BYTES (64u << 20)
+int wave_forward_noalloc(const wave_grid* grid, const float* m, const float* eta,
+                         const wave_points* src, const float* q,
+                         const wave_points* rec, float* d, float* u_final, void* stream);
+
+/*
  * Adjoint modelling (listing "lst:adjoint": the eta term enters with the
  * opposite sign and the update is solved for the backward level).  Driven by
  * receiver data, sampled at the sources; it is the exact transpose of the

@@ -19,6 +19,7 @@ WAVE_OK, WAVE_EINVAL, WAVE_ECFL, WAVE_ERANGE, WAVE_EWORKSPACE, WAVE_EHIP = 0, -1
 WAVE_OP_FORWARD, WAVE_OP_ADJOINT, WAVE_OP_GRADIENT, WAVE_OP_FORWARD_CKPT, WAVE_OP_BACKWARD = \
     0, 1, 2, 3, 4
 WAVE_MISFIT_WORKSPACE_BYTES = 4096
+WAVE_NOALLOC_WORKSPACE_BYTES = 64 << 20
 CKPT_DTYPES = {"fp32": 0, "bf16": 1, "fp16": 2}
 _NAMES = {0: "WAVE_OK", -1: "WAVE_EINVAL", -2: "WAVE_ECFL", -3: "WAVE_ERANGE",
           -4: "WAVE_EWORKSPACE", -5: "WAVE_EHIP"}
@@ -27,7 +28,7 @@ EXPORTS = ["wave_workspace_size", "wave_checkpoint_size", "wave_forward", "wave_
            "wave_backward", "wave_gradient", "wave_batch_workspace_size", "wave_forward_batch",
            "wave_tune", "wave_tune_batch", "wave_last_batch_mode", "wave_diffusion",
            "wave_set_profiling", "wave_last_loop", "wave_misfit", "wave_release",
-           "wave_tile_candidates", "wave_resolve_tile",
+           "wave_tile_candidates", "wave_resolve_tile", "wave_forward_noalloc",
            "wave_last_error", "wave_version"]
 WAVE_FLAG_NO_GRAPH = 1
 WAVE_FLAG_PERSISTENT = 2
@@ -103,6 +104,8 @@ def lib():
         L.wave_tile_candidates.restype = C.c_int
         L.wave_resolve_tile.argtypes = [P(Grid), I32, P(C.c_int32)]
         L.wave_resolve_tile.restype = C.c_int
+        L.wave_forward_noalloc.argtypes = [P(Grid), VP, VP, P(Points), VP, P(Points), VP, VP, VP]
+        L.wave_forward_noalloc.restype = C.c_int
         L.wave_release.argtypes = []
         L.wave_release.restype = C.c_int
         L.wave_last_error.restype = C.c_char_p

@@ -556,9 +556,14 @@ int staging(size_t bytes, char** out)
 }
 
 // Common set-up: sparse tables, uploads, field validation and coefficients
-// (one pass over m and eta), then the only wait of the call.
+// (one pass over m and eta), then the only wait of the call.  With `noalloc`
+// the workspace is the library's own device array (wave_forward_noalloc) and
+// the uploads and the read-back go through ordinary host memory instead of
+// the pinned staging buffer, so that nothing is allocated on the device or
+// pinned on the host.
 int setup(Ctx& C, int op, const wave_grid* grid, const float* m, const float* eta,
-          const wave_points* src, const wave_points* rec, const wave_opts* o, void* stream)
+          const wave_points* src, const wave_points* rec, const wave_opts* o, void* stream,
+          bool noalloc = false)
 {
     int rc = make_geo(grid, &C.G);
     if (rc) return rc;
@@ -566,8 +571,19 @@ int setup(Ctx& C, int op, const wave_grid* grid, const float* m, const float* et
     if ((rc = make_points(C.G, rec, "receiver", &C.rec))) return rc;
     if ((rc = make_points(C.G, src, "source", &C.src))) return rc;
     C.P = make_plan(op, C.G, C.src.npts, C.rec.npts, o);
-    if ((rc = check_ws(C.P, o))) return rc;
-    C.ws = static_cast<char*>(o->workspace);
+    if (noalloc) {
+        if (C.P.total > kNoAllocBytes)
+            return fail(WAVE_EWORKSPACE,
+                        "this grid and point set need %zu bytes of workspace; the no-allocation "
+                        "entry point has %zu (use wave_forward with a caller workspace)",
+                        C.P.total, kNoAllocBytes);
+        void* p = nullptr;
+        HIP_TRY(noalloc_scratch(&p));
+        C.ws = static_cast<char*>(p);
+    } else {
+        if ((rc = check_ws(C.P, o))) return rc;
+        C.ws = static_cast<char*>(o->workspace);
+    }
     C.s = static_cast<hipStream_t>(stream);
     if ((rc = pick_tile(o, tune_key(C.G, false), C.G, &C.cfg))) return rc;
     if ((rc = pick_tile(o, tune_key(C.G, true), C.G, &C.cfg_img))) return rc;
@@ -600,7 +616,14 @@ int setup(Ctx& C, int op, const wave_grid* grid, const float* m, const float* et
     size_t total = part_bytes;
     for (const Up& u : ups) total += round_up(u.bytes, 64);
     char* host = nullptr;
-    if ((rc = staging(total, &host))) return rc;
+    std::vector<char> pageable;
+    if (noalloc) {
+        // pageable memory: the copies complete by the wait below, while it lives
+        pageable.resize(total);
+        host = pageable.data();
+    } else if ((rc = staging(total, &host))) {
+        return rc;
+    }
     float* part = reinterpret_cast<float*>(host);
     size_t off = part_bytes;
     for (const Up& u : ups) {
@@ -612,7 +635,7 @@ int setup(Ctx& C, int op, const wave_grid* grid, const float* m, const float* et
                                 kCheckBlocks, C.at<float>(C.P.alpha), C.at<float>(C.P.beta),
                                 C.G.dt, C.s));
     HIP_TRY(hipMemcpyAsync(part, C.at<float>(C.P.check), part_bytes, hipMemcpyDeviceToHost, C.s));
-    HIP_TRY(hipEventRecord(TS().stage.done, C.s));
+    if (!noalloc) HIP_TRY(hipEventRecord(TS().stage.done, C.s));
     HIP_TRY(hipStreamSynchronize(C.s));
     float mmin = INFINITY, bad = 0;
     for (int b = 0; b < kCheckBlocks; ++b) {
@@ -1325,6 +1348,26 @@ int wave_forward(const wave_grid* grid, const float* m, const float* eta, const 
         CkptView ck;
         if (ckpt) ck = ckpt_view(C.G, opts, ckpt);
         return run_forward(C, q, d, u_final, ckpt ? &ck : nullptr, true);
+    } catch (const std::exception& e) {
+        return fail(WAVE_EINVAL, "exception: %s", e.what());
+    } catch (...) {
+        return fail(WAVE_EINVAL, "unknown exception");
+    }
+}
+
+int wave_forward_noalloc(const wave_grid* grid, const float* m, const float* eta,
+                         const wave_points* src, const float* q, const wave_points* rec, float* d,
+                         float* u_final, void* stream)
+{
+    try {
+        Ctx C;
+        wave_opts o;
+        std::memset(&o, 0, sizeof o);
+        if (src && src->npts > 0 && !q) return fail(WAVE_EINVAL, "q is NULL with %d sources", src->npts);
+        if (rec && rec->npts > 0 && !d) return fail(WAVE_EINVAL, "d is NULL with %d receivers", rec->npts);
+        int rc = setup(C, WAVE_OP_FORWARD, grid, m, eta, src, rec, &o, stream, true);
+        if (rc) return rc;
+        return run_forward(C, q, d, u_final, nullptr, true);
     } catch (const std::exception& e) {
         return fail(WAVE_EINVAL, "exception: %s", e.what());
     } catch (...) {

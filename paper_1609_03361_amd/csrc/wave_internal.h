@@ -85,6 +85,14 @@ struct TileCfg {
 inline TileCfg tile_from_id(int id) { TileCfg c; c.variant = (id >> 16) & 0xff; c.xchunk = id & 0xffff; return c; }
 inline int tile_id(const TileCfg& c) { return (c.variant << 16) | c.xchunk; }
 
+// Size of the device array that serves as the workspace of
+// wave_forward_noalloc, and how many devices' addresses of it are kept.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+// Device address of that array on the current device (looked up once per
+// device with hipGetSymbolAddress).
+hipError_t noalloc_scratch(void** ptr);
+
 // Rows of u^n a 2D slab block computes at most (its x-chunk); the LDS slab
 // holds them with R halo rows on either side.
 constexpr int kSlabRows = 16;

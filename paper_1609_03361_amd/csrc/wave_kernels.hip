@@ -3,12 +3,39 @@
 // codec, plus the dispatch over the space order to the step kernels (each
 // order in its own translation unit, wave_o<order>.hip, from wave_step.h).
 #include <algorithm>
+#include <mutex>
 
 #include <hip/hip_fp16.h>
 
 #include "wave_internal.h"
 
 namespace wave {
+
+// Workspace of wave_forward_noalloc: a device array of the library's own, so
+// that the call allocates nothing.  Host code never uses the array's name as
+// an address (on the host it is only a stand-in for the symbol): the device
+// address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+hipError_t noalloc_scratch(void** ptr)
+{
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
 
 namespace {
 

@@ -92,8 +92,11 @@ typedef struct {
                                  2 = 128 z (2 per lane), 3 = 256 z with x-chunks of at most
                                  16 rows held in LDS; 3D 0 = 64 x 16, 1 = 64 x 8,
                                  2 = 32 x 32, 3 = 100 x 10, 4 = 200 x 5 (4 z-points per
-                                 lane), 5 = 64 x 8 (2 per lane).  An unknown variant or a
-                                 negative id is WAVE_EINVAL.  Results do not depend on it. */
+                                 lane), 5 = 64 x 8 (2 per lane), 6 = 64 x 32 (4 per lane),
+                                 7 = 64 x 16, 8 = 64 x 32 (2 per lane), 9 = 128 x 16
+                                 (4 per lane), 10 = 128 x 16 (2 per lane).  An unknown
+                                 variant or a negative id is WAVE_EINVAL.  Results do not
+                                 depend on it. */
     int32_t flags;            /* WAVE_FLAG_* bits */
 } wave_opts;
 
@@ -261,7 +264,9 @@ int wave_last_batch_mode(void);
  * fastest in a process-wide cache that calls with opts->tile == 0 consult
  * (mirrored to the file named by the environment variable WAVE_TUNE_CACHE),
  * and returns its id and its time per step in microseconds.  Candidates give
- * bitwise identical results; no output buffer is written.
+ * bitwise identical results; no output buffer is written.  With the
+ * environment variable WAVE_TUNE_VERBOSE set, every candidate's time is
+ * printed to stderr.
  */
 int wave_tune(const wave_grid* grid, const wave_opts* opts, int32_t steps, void* stream,
               int32_t* tile, double* us_per_step);
@@ -275,8 +280,9 @@ int wave_tune_batch(int32_t nshots, const wave_shot* shots, const wave_opts* opt
 int wave_tile_candidates(const wave_grid* grid, int32_t* ids, int32_t cap, int32_t* n);
 /* The tile a step launch on this grid uses for the requested id (0 = the
  * tuned or default one): its block shape and its x-chunk after clamping and
- * planning.  For an x-chunk of 0 the plan is the one made without the
- * device's occupancy figure, which a launch may refine.  Host only. */
+ * planning.  For an x-chunk of 0, the plan depends on the kernel's occupancy
+ * on the current device; without a device the occupancy-free plan is
+ * returned. */
 int wave_resolve_tile(const wave_grid* grid, int32_t tile, int32_t* resolved);
 
 /*

@@ -25,12 +25,20 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, out_dir: str = OUT, defines=(), jobs: int = 0) -> str:
-    """Compile libwave.so into ``out_dir`` (extra ``-D`` defines for tuning builds)."""
+def build(verbose: bool = False, out_dir: str = OUT, defines=(), jobs: int = 0, orders=ORDERS,
+          extra_flags=()) -> str:
+    """Compile libwave.so into ``out_dir``.  ``defines`` and ``orders`` serve
+    experimental builds (extra ``-D`` knobs; a single space order, which then
+    also restricts the order dispatch)."""
     os.makedirs(out_dir, exist_ok=True)
     lib = os.path.join(out_dir, "libwave.so")
     jobs = jobs or int(os.environ.get("MAX_JOBS", "0")) or os.cpu_count() or 4
-    pending = list(SOURCES)
+    orders = tuple(orders)
+    if orders != ORDERS:
+        if len(orders) != 1:
+            raise ValueError("an experimental build holds all orders or exactly one")
+        defines = tuple(defines) + (f"WAVE_ONLY_ORDER={orders[0]}",)
+    pending = ["wave_host.cpp", "wave_kernels.hip"] + [f"wave_o{o}.hip" for o in orders]
     running = []
     objs = []
     failed = []
@@ -38,8 +46,8 @@ def build(verbose: bool = False, out_dir: str = OUT, defines=(), jobs: int = 0) 
         while pending and len(running) < jobs:
             src = pending.pop(0)
             obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
-            cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src),
-                   "-o", obj]
+            cmd = [HIPCC, *FLAGS, *extra_flags, *[f"-D{d}" for d in defines], "-c",
+                   os.path.join(CSRC, src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
             running.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE,

@@ -169,6 +169,8 @@ int make_geo(const wave_grid* g, Geo* G)
     if (total > 4.0e10) return fail(WAVE_EINVAL, "grid has too many points");
     if ((double)G->n[0] * (double)G->n[1] >= 2147483647.0)
         return fail(WAVE_EINVAL, "nx * ny must be below 2^31");
+    if ((double)G->n[1] * (double)G->nzp >= 2147483647.0)
+        return fail(WAVE_EINVAL, "ny * nz must be below 2^31");
     return WAVE_OK;
 }
 
@@ -370,8 +372,17 @@ Plan make_plan(int op, const Geo& G, int nsrc, int nrec, const wave_opts* o)
     Carver c;
     const size_t N = (size_t)G.npad();
     const int nc = 1 << G.ndim;
+#ifdef WAVE_EXP_TABLES_LAST
+    Carver big;
+    P.alpha = big.take(N * 4 + WAVE_EXP_FIELD_GAP);
+    P.beta = big.take(N * 4 + WAVE_EXP_FIELD_GAP);
+    P.wf[0] = big.take(N * 4 + WAVE_EXP_FIELD_GAP);
+    P.wf[1] = big.take(N * 4 + WAVE_EXP_FIELD_GAP);
+    c.off = big.off;
+#else
     P.alpha = c.take(N * 4);
     P.beta = c.take(N * 4);
+#endif
     P.check = c.take((size_t)kCheckBlocks * 3 * 4);
     // sparse tables: the forward (and the backward's replay) samples receivers
     // and injects sources, the adjoint the other way round
@@ -389,10 +400,12 @@ Plan make_plan(int op, const Geo& G, int nsrc, int nrec, const wave_opts* o)
         P.inj_ptr[s] = c.take(iuse[s] ? ((size_t)G.nrows() + 1) * 4 : 0);
         P.inj_ent[s] = c.take((size_t)ipt[s] * nc * sizeof(InjEntry));
     }
+#ifndef WAVE_EXP_TABLES_LAST
     if (op == WAVE_OP_FORWARD || op == WAVE_OP_FORWARD_CKPT || op == WAVE_OP_GRADIENT) {
         P.wf[0] = c.take(N * 4);
         P.wf[1] = c.take(N * 4);
     }
+#endif
     if (adj) {
         P.adj[0] = c.take(N * 4);
         P.adj[1] = c.take(N * 4);
@@ -668,12 +681,30 @@ StepArgs base_args(const Ctx& C)
 
 // set = 0: sources inject (forward), receivers sample; set = 1: receivers
 // inject (adjoint), sources sample.
+// The planes x and rows y that an injected point set touches: every corner
+// node lies in [min x0, max x0 + 1] x [min y0, max y0 + 1] over the points'
+// cells (2D: rows are all 0; empty set: x1 < x0).
+void inj_planes(const HostPoints& P, StepArgs& a)
+{
+    a.inj_x0 = a.inj_y0 = 1;
+    a.inj_x1 = a.inj_y1 = 0;
+    for (int p = 0; p < P.npts; ++p) {
+        const int64_t x = P.cell[(size_t)p * 3], y = P.cell[(size_t)p * 3 + 1];
+        const int64_t y1 = a.ny > 1 ? y + 1 : y;
+        if (p == 0 || x < a.inj_x0) a.inj_x0 = x;
+        if (p == 0 || x + 1 > a.inj_x1) a.inj_x1 = x + 1;
+        if (p == 0 || y < a.inj_y0) a.inj_y0 = y;
+        if (p == 0 || y1 > a.inj_y1) a.inj_y1 = y1;
+    }
+}
+
 void bind_sparse(const Ctx& C, StepArgs& a, int set)
 {
     const int inj = set == 0 ? 0 : 1;
     const int smp = set == 0 ? 0 : 1;
     a.inj.row_ptr = C.at<int32_t>(C.P.inj_ptr[inj]);
     a.inj.ent = C.at<InjEntry>(C.P.inj_ent[inj]);
+    inj_planes(set == 0 ? C.src : C.rec, a);
     a.smp.base = C.at<int64_t>(C.P.smp_base[smp]);
     a.smp.w = C.at<float>(C.P.smp_w[smp]);
     a.smp.npts = set == 0 ? C.rec.npts : C.src.npts;
@@ -832,17 +863,19 @@ int run_backward(const Ctx& C, const float* q, const float* r, const CkptView& c
 // result (the per-point arithmetic does not depend on the tiling).
 // ---------------------------------------------------------------------------
 // Candidate tiles: every block shape with x-chunks of 2R, 4R, 8 .. 128
-// planes, each clamped to what the shape accepts (the 2D slab holds at most
-// 16 rows) and to the grid, so that no two candidates launch the same thing.
+// planes and of a half, a third and a quarter of the grid, each clamped to
+// what the shape accepts (the 2D slab holds at most 16 rows) and to the grid,
+// so that no two candidates launch the same thing.
 std::vector<TileCfg> tile_candidates(int ndim, int half, int64_t nx, int64_t nz)
 {
     std::vector<TileCfg> out;
-    const int xs[] = {2 * half, 4 * half, 8, 16, 32, 64, 128};
+    const int64_t xs[] = {2 * half, 4 * half, 8, 16, 32, 64, 128, (nx + 1) / 2, (nx + 2) / 3, (nx + 3) / 4};
     for (int v = 0; v < tile_variants(ndim, nz); ++v)
-        for (int x : xs) {
+        for (int64_t x : xs) {
+            if (x < 2 * half) continue;
             TileCfg c;
             c.variant = v;
-            c.xchunk = (int)std::min<int64_t>(std::min(x, max_xchunk(ndim, v)), nx);
+            c.xchunk = (int)std::min<int64_t>(std::min<int64_t>(x, max_xchunk(ndim, v)), std::min<int64_t>(nx, 0xffff));
             bool dup = false;
             for (const TileCfg& o : out) dup = dup || (o.variant == c.variant && o.xchunk == c.xchunk);
             if (!dup) out.push_back(c);
@@ -939,6 +972,7 @@ StepArgs shot_args(const BatchShot& S, char* ws)
     a.inv_dt2 = (float)(1.0 / (S.G.dt * S.G.dt));
     a.inj.row_ptr = reinterpret_cast<int32_t*>(ws + S.inj_ptr);
     a.inj.ent = reinterpret_cast<InjEntry*>(ws + S.inj_ent);
+    inj_planes(S.src, a);
     a.smp.base = reinterpret_cast<int64_t*>(ws + S.smp_base);
     a.smp.w = reinterpret_cast<float*>(ws + S.smp_w);
     a.smp.npts = S.rec.npts;
@@ -1258,7 +1292,12 @@ int wave_resolve_tile(const wave_grid* grid, int32_t tile, int32_t* resolved)
         StepArgs a;
         std::memset(&a, 0, sizeof a);
         a.nx = G.n[0]; a.ny = G.n[1]; a.nz = G.nzp;
-        if (plan_tiles(G.ndim, G.order, cfg, a) < 0) return fail(WAVE_EINVAL, "tile %d cannot be planned", tile);
+        // with a device present, the plan a launch on it makes (occupancy-sized
+        // x-chunks); without one, the occupancy-free plan
+        int ndev = 0;
+        const bool device = hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0;
+        if (plan_tiles(G.ndim, G.order, cfg, a, device) < 0)
+            return fail(WAVE_EINVAL, "tile %d cannot be planned", tile);
         TileCfg out = cfg;
         out.xchunk = a.xchunk;
         *resolved = tile_id(out);
@@ -1554,6 +1593,7 @@ int wave_tune(const wave_grid* grid, const wave_opts* opts, int32_t steps, void*
         HIP_TRY(hipEventCreate(&ev.b));
         double best = 1e300;
         TileCfg best_cfg;
+        const bool verbose = std::getenv("WAVE_TUNE_VERBOSE") != nullptr;
         for (const TileCfg& cfg : tile_candidates(C.G.ndim, C.G.half, C.G.n[0], C.G.nzp)) {
             for (int w = 0; w < 2; ++w) HIP_TRY(launch_step(C.G.ndim, C.G.order, a, C.s, cfg));
             double t = 1e300;
@@ -1566,6 +1606,9 @@ int wave_tune(const wave_grid* grid, const wave_opts* opts, int32_t steps, void*
                 HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
                 t = std::min(t, 1e3 * ms / steps);
             }
+            if (verbose)
+                std::fprintf(stderr, "wave_tune %s: variant %d x-chunk %d: %.2f us\n",
+                             imaging ? "imaging" : "step", cfg.variant, cfg.xchunk, t);
             if (t < best) { best = t; best_cfg = cfg; }
         }
         *tile = tile_id(best_cfg);

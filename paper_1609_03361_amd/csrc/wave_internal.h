@@ -50,6 +50,10 @@ struct StepArgs {
     // sampling of `cur` (values for this step)
     SampleSet smp;
     float* smp_out;        // [npts] for this step, or nullptr
+    // injected nodes lie in planes [inj_x0, inj_x1] and rows [inj_y0, inj_y1]
+    // (empty when inj_x1 < inj_x0): blocks outside skip injection without a
+    // memory lookup
+    int64_t inj_x0, inj_x1, inj_y0, inj_y1;
     int64_t stencil_blocks;
     // streaming-kernel tiling (set by the launcher): tiles along z and y,
     // x-chunk length, and whether the single-shot grid pads its tile part to
@@ -108,18 +112,23 @@ constexpr int kSlabRows = 16;
 //   3D, four z-points per lane: 64 z x 16 rows, 64 z x 8 rows, 32 z x 32
 //   rows, 100 z x 10 rows or 200 z x 5 rows (the last two cover grids such as
 //   200^3 without a mostly empty last tile); two z-points per lane: 64 z x 8
-//   rows (half the queue registers per lane).
+//   rows (half the queue registers per lane).  Taller tiles for the high
+//   orders, where the y halo (R rows on either side) is as large as a 16-row
+//   tile: 64 z x 32 rows (four points per lane), 64 z x 16 and 64 z x 32 rows
+//   (two points per lane), 128 z x 16 rows (four and two points per lane).
 struct BlockShape {
     int vz, tzl, ty;
 };
 constexpr BlockShape kShapes2D[] = {{4, 64, 1}, {1, 128, 1}, {2, 64, 1}, {4, 64, 8}};
-constexpr BlockShape kShapes3D[] = {{4, 16, 16}, {4, 16, 8}, {4, 8, 32}, {4, 25, 10}, {4, 50, 5}, {2, 32, 8}};
+constexpr BlockShape kShapes3D[] = {{4, 16, 16}, {4, 16, 8}, {4, 8, 32}, {4, 25, 10}, {4, 50, 5},
+                                    {2, 32, 8},  {4, 16, 32}, {2, 32, 16}, {2, 32, 32}, {4, 32, 16},
+                                    {2, 64, 16}};
 
 // The step kernels of one space order O (defined in wave_step.h, instantiated
 // in wave_o<O>.hip); the launch_* functions below dispatch to them.
 template <int O>
 struct OrderOps {
-    static int64_t plan(int ndim, TileCfg cfg, StepArgs& a);
+    static int64_t plan(int ndim, TileCfg cfg, StepArgs& a, bool device);
     static hipError_t step(int ndim, const StepArgs& a, hipStream_t s, TileCfg cfg);
     static hipError_t batch(int ndim, int64_t nz_any, TileCfg cfg, const ShotDesc* shots,
                             const int64_t* begin, int32_t nshots, int64_t blocks, int32_t n,
@@ -147,7 +156,10 @@ int max_xchunk(int ndim, int variant);
 int default_variant(int ndim, int order, int64_t ny, int64_t nz);
 // Fill the tiling fields of `a` (ntz, nty, xchunk, stencil_blocks, remap) for
 // `cfg`; returns the block count of one launch including receiver samplers.
-int64_t plan_tiles(int ndim, int order, TileCfg cfg, StepArgs& a);
+// With `device` the plan is the one a single-shot launch on the current
+// device makes (x-chunks from the kernel's occupancy); without, the
+// occupancy-free plan of the many-shot launches.
+int64_t plan_tiles(int ndim, int order, TileCfg cfg, StepArgs& a, bool device = false);
 
 // Launch one time step of the 2.5D streaming kernel (plans `a` for cfg).
 hipError_t launch_step(int ndim, int order, const StepArgs& a, hipStream_t s, TileCfg cfg);

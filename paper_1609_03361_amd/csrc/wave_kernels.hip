@@ -385,11 +385,15 @@ int default_variant(int ndim, int order, int64_t ny, int64_t nz)
     if (ndim == 2) return 3;      // the slab body (2001 x 801 order 8: 8.7 us against 10.9 us per step)
     // Candidates in order of preference at equal lane waste: up to order 8
     // the two-point-lane tile first (256^3 order 8: 52.2 us against 53.8 us
-    // for 64 z x 16 rows of four-point lanes); above, it is slower (512^3
-    // order 16: 596 us against 561 us).
-    const int pref[] = {5, 0, 1, 2, 3, 4};
-    const int base[] = {0, 1, 2, 3, 4, 5};
-    const int* order_of = order <= 8 ? pref : base;
+    // for 64 z x 16 rows of four-point lanes); at orders 14 and 16 the
+    // two-point-lane 64 z x 16 tile (512^3 order 16, real fields: 470 us with
+    // x-chunks of 256 planes against 520 us for 64 z x 16 of four-point lanes).
+    const int pref[] = {5, 0, 1, 2, 3, 4, 6, 7, 8, 9, 10};
+    const int base[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10};
+    const int high[] = {7, 0, 1, 2, 3, 4, 5, 6, 8, 9, 10};
+    static_assert(sizeof pref / sizeof pref[0] == sizeof kShapes3D / sizeof kShapes3D[0], "");
+    static_assert(sizeof high / sizeof high[0] == sizeof kShapes3D / sizeof kShapes3D[0], "");
+    const int* order_of = order <= 8 ? pref : (order >= 14 ? high : base);
     int best = 0;
     double best_eff = -1.0;
     for (int k = 0; k < tile_variants(3, nz); ++k) {
@@ -406,11 +410,15 @@ int default_variant(int ndim, int order, int64_t ny, int64_t nz)
 }
 
 // Order dispatch: each space order's kernels live in their own translation unit.
+#ifdef WAVE_ONLY_ORDER
+#define WAVE_ORDERS(X) X(WAVE_ONLY_ORDER)      // experimental builds of one order
+#else
 #define WAVE_ORDERS(X) X(2) X(4) X(6) X(8) X(10) X(12) X(14) X(16)
+#endif
 
-int64_t plan_tiles(int ndim, int order, TileCfg cfg, StepArgs& a)
+int64_t plan_tiles(int ndim, int order, TileCfg cfg, StepArgs& a, bool device)
 {
-#define WAVE_CASE(O) case O: return OrderOps<O>::plan(ndim, cfg, a);
+#define WAVE_CASE(O) case O: return OrderOps<O>::plan(ndim, cfg, a, device);
     switch (order) { WAVE_ORDERS(WAVE_CASE) default: return -1; }
 #undef WAVE_CASE
 }

@@ -22,6 +22,16 @@
 
 #include "wave_internal.h"
 
+// Build-time knobs of the streaming body (defaults measured best): planes of
+// per-plane operands in flight in 3D, and the largest half-width with the
+// halo lead.
+#ifndef WAVE_PRE_RING_3D
+#define WAVE_PRE_RING_3D 2
+#endif
+#ifndef WAVE_LEAD_MAX_R
+#define WAVE_LEAD_MAX_R 6
+#endif
+
 namespace wave {
 
 namespace {
@@ -134,12 +144,12 @@ struct Tile {
     // ring is deeper there (measured: 2.5 % on the batched 2D shots).  PR
     // divides S so that the unrolled group of S planes addresses every slot
     // at a compile-time index.
-    static constexpr int PR = DIM == 2 ? pre_ring(S, 4) : 2;
+    static constexpr int PR = DIM == 2 ? pre_ring(S, 4) : WAVE_PRE_RING_3D;
     // Halo lead: in 3D, the y/z halo of plane p is loaded together with the
     // queue load of p (R+1 planes before its use) and held in registers, so it
     // is read while the neighbouring tile's load of the same rows is still in
     // L2.  Above R = 6 the extra registers would cost occupancy.
-    static constexpr bool LEAD = DIM == 3 && R <= 6;
+    static constexpr bool LEAD = DIM == 3 && R <= WAVE_LEAD_MAX_R;
     static constexpr bool HINT = !LEAD;
     // 2D with TY > 1: the slab body (TY waves share one x-chunk held in LDS)
     static constexpr bool SLAB = DIM == 2 && TY > 1;
@@ -173,15 +183,44 @@ __device__ __forceinline__ void z_terms(const float* Lc, const Vec<VZ>& c, const
             lap[v] = fmaf(cz[j], (zr[RZ + v + j] + zr[RZ + v - j]) + m2c[v], lap[v]);
 }
 
+// Owner-gather injection of the entries [e0, e1) of a lane's row into its VZ
+// points z .. z+VZ-1: o += alpha * sum_e w_e val[pt_e] over the entries at
+// each point, summed in entry order (sorted by point index).  One entry at a
+// time: loading several ahead held enough registers to cost the 512^3
+// order-16 step a wave per SIMD.
+template <int VZ>
+__device__ __forceinline__ void inject_entries(const StepArgs& a, int32_t e0, int32_t e1, int64_t z,
+                                               const Vec<VZ>& al, Vec<VZ>& o)
+{
+    float acc[VZ];
+    bool hit[VZ];
+#pragma unroll
+    for (int v = 0; v < VZ; ++v) { acc[v] = 0.f; hit[v] = false; }
+    for (int32_t e = e0; e < e1; ++e) {
+        const InjEntry en = a.inj.ent[e];
+        const int64_t dz = (int64_t)en.z - z;
+#pragma unroll
+        for (int v = 0; v < VZ; ++v)
+            if (dz == v) {
+                acc[v] = fmaf(en.w, a.inj_val[en.pt], acc[v]);
+                hit[v] = true;
+            }
+    }
+#pragma unroll
+    for (int v = 0; v < VZ; ++v)
+        if (hit[v]) o[v] = fmaf(al[v], acc[v], o[v]);
+}
+
 // The leapfrog update of the VZ points of one lane, then the owner-gather
-// injection of the sources on row (x, y) (only when the block's x-range holds
-// any, `inj_any`, and plane x does).  The streaming body spells out the same
-// operations inline (as a call here it held two more registers per lane,
-// which cost a wave per SIMD); the tile tests check the two bit for bit.
+// injection of the entries [e0, e1) of the lane's row (e1 == e0 when the row
+// holds no injected node; the range was fetched with the other per-row
+// operands).  The streaming body spells out the same operations inline (as a
+// call here it held two more registers per lane, which cost a wave per
+// SIMD); the tile tests check the two bit for bit.
 template <int VZ>
 __device__ __forceinline__ Vec<VZ> update_inject(const StepArgs& a, const Vec<VZ>& c, const float* lap,
                                                  const Vec<VZ>& uo, const Vec<VZ>& al, const Vec<VZ>& be,
-                                                 bool inj_any, bool own, int64_t x, int64_t y, int64_t z)
+                                                 int32_t e0, int32_t e1, int64_t z)
 {
     Vec<VZ> o;
 #pragma unroll
@@ -189,34 +228,13 @@ __device__ __forceinline__ Vec<VZ> update_inject(const StepArgs& a, const Vec<VZ
         const float w = fmaf(be[v], c[v] - uo[v], c[v]);
         o[v] = fmaf(al[v], lap[v], w);
     }
-    if (inj_any) {
-        // planes without injected nodes skip the per-row lookup (uniform test)
-        const int64_t ny = a.ny;
-        const int32_t* rp = a.inj.row_ptr;
-        if (rp[(x + 1) * ny] != rp[x * ny] && own) {
-            const int64_t row = x * ny + y;
-            const int32_t e0 = rp[row], e1 = rp[row + 1];
-            float acc[VZ];
-            bool hit[VZ];
-#pragma unroll
-            for (int v = 0; v < VZ; ++v) { acc[v] = 0.f; hit[v] = false; }
-            for (int32_t e = e0; e < e1; ++e) {
-                const InjEntry en = a.inj.ent[e];
-                const int64_t dz = (int64_t)en.z - z;
-#pragma unroll
-                for (int v = 0; v < VZ; ++v)
-                    if (dz == v) {
-                        acc[v] = fmaf(en.w, a.inj_val[en.pt], acc[v]);
-                        hit[v] = true;
-                    }
-            }
-#pragma unroll
-            for (int v = 0; v < VZ; ++v)
-                if (hit[v]) o[v] = fmaf(al[v], acc[v], o[v]);
-        }
-    }
+    if (e1 > e0) inject_entries<VZ>(a, e0, e1, z, al, o);
     return o;
 }
+
+// Planes of an x-chunk whose injection flags a streaming block keeps in LDS
+// (one bit per plane); planes beyond them are looked up in the row pointers.
+constexpr int kInjMaskWords = 64;
 
 // One block's share of one time step: tile (tzi, tyi) of the (y, z) plane over
 // x-chunk `chunk`, where L = (chunk * nty + tyi) * ntz + tzi.
@@ -239,7 +257,8 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, int64_t L)
     const int64_t y0 = (int64_t)tyi * TY, z0 = (int64_t)tzi * TZ;
     const int64_t y = y0 + ty, z = z0 + (int64_t)tz * VZ;
     const bool own = (y < ny) && (z < nz);
-    const int64_t col = y * sy + z;
+    // offsets within a (y, z) plane fit 32 bits (the library checks ny * nz < 2^31)
+    const int32_t col = (int32_t)(y * sy + z);
     const int64_t xa = chunk * a.xchunk;
     const int64_t xb = xa + a.xchunk < nx ? xa + a.xchunk : nx;
     // Odd chunks walk x downwards: the 2R planes two neighbouring chunks both
@@ -254,7 +273,7 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, int64_t L)
     const int64_t x0 = dir > 0 ? xa : xb - 1;
 
     // halo items of this thread: plane offset (or -1 when outside the grid) and LDS slot
-    int64_t hoff[KH];
+    int32_t hoff[KH];
     int hlds[KH];
 #pragma unroll
     for (int k = 0; k < KH; ++k) {
@@ -266,7 +285,7 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, int64_t L)
             const int64_t yy = hr < R ? y0 - R + hr : y0 + TY + (hr - R);
             const int64_t zz = z0 + (int64_t)hz * VZ;
             hlds[k] = (hr < R ? hr : hr + TY) * PITCH + RZ + hz * VZ;
-            if (yy >= 0 && yy < ny && zz < nz) hoff[k] = yy * sy + zz;
+            if (yy >= 0 && yy < ny && zz < nz) hoff[k] = (int32_t)(yy * sy + zz);
         } else if (i < T::NHY + T::NHZ) {
             constexpr int PER = RZ / VZ;
             const int j = i - T::NHY;
@@ -274,7 +293,7 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, int64_t L)
             const int64_t yy = y0 + r;
             const int64_t zz = side == 0 ? z0 - RZ + (int64_t)kk * VZ : z0 + TZ + (int64_t)kk * VZ;
             hlds[k] = (r + (DIM == 3 ? R : 0)) * PITCH + (side == 0 ? kk * VZ : RZ + TZ + kk * VZ);
-            if (yy < ny && zz >= 0 && zz < nz) hoff[k] = yy * sy + zz;
+            if (yy < ny && zz >= 0 && zz < nz) hoff[k] = (int32_t)(yy * sy + zz);
         }
     }
 
@@ -291,11 +310,36 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, int64_t L)
     for (int k = 0; k < 2 * R + 1; ++k) Q[k] = center(x0 + dir * (k - R));
     Q[S - 1] = vzero<VZ>();
 
+    // Injection: does any injected node lie in this block's x-range (uniform;
+    // most blocks of a forward run have none), and which planes hold one (a
+    // bit per plane in LDS, filled once), so that a plane's row lookup is a
+    // per-row operand fetched ahead with the others instead of a dependent
+    // load on every plane.
+    const int32_t* rp = a.inj.row_ptr;
+    const bool inj_any = a.inj_val && xb > a.inj_x0 && xa <= a.inj_x1 &&
+                         y0 + TY > a.inj_y0 && y0 <= a.inj_y1;
+    __shared__ uint32_t inj_mask[kInjMaskWords];
+    if (inj_any) {
+        for (int w = tid; w < kInjMaskWords; w += NT) inj_mask[w] = 0u;
+        lds_barrier();
+        for (int64_t i = tid; i < count && i < 32 * kInjMaskWords; i += NT) {
+            const int64_t xx = xa + i;
+            if (rp[(xx + 1) * ny] != rp[xx * ny]) atomicOr(&inj_mask[i >> 5], 1u << (i & 31));
+        }
+        lds_barrier();
+    }
+    auto plane_has_inj = [&](int64_t xx) -> bool {
+        const int64_t i = xx - xa;
+        if (i < 32 * kInjMaskWords) return (inj_mask[i >> 5] >> (i & 31)) & 1u;
+        return rp[(xx + 1) * ny] != rp[xx * ny];
+    };
+
     // per-plane operands, fetched PR-1 planes ahead of their use
     struct Pre {
         Vec<VZ> halo[KH];
         Vec<VZ> uo, al, be;
         Vec<VZ> fw, gr;          // imaging: forward wavefield u^k and gradient
+        int32_t e0, e1;          // injection entries of the lane's row
     };
     Pre pre[PR];
     // halo ring of the lead mode (one slot per plane of lead)
@@ -326,6 +370,12 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, int64_t L)
                 P.gr = vload_once<VZ, T::HINT>(a.img_grad + xx * sx + col);
             }
         }
+        P.e0 = P.e1 = 0;
+        if (inj_any && own && plane_has_inj(xx)) {
+            const int64_t row = xx * ny + y;
+            P.e0 = rp[row];
+            P.e1 = rp[row + 1];
+        }
     };
 #pragma unroll
     for (int k = 0; k < PR - 1; ++k)
@@ -336,9 +386,6 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, int64_t L)
     }
 
     const int row_c = (ty + (DIM == 3 ? R : 0)) * PITCH + RZ + tz * VZ;
-    // does any injected node lie in this block's x-range? (uniform; most
-    // blocks of a forward run have none and skip the per-plane lookup)
-    const bool inj_any = a.inj_val && a.inj.row_ptr[xb * ny] != a.inj.row_ptr[xa * ny];
 
     // one plane; U is the position within the unrolled group of S planes
     auto plane = [&](auto UC, int64_t i) {
@@ -413,31 +460,7 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, int64_t L)
             const float w = fmaf(P.be[v], c[v] - P.uo[v], c[v]);
             o[v] = fmaf(P.al[v], lap[v], w);
         }
-        if (inj_any) {
-            // planes without injected nodes skip the per-row lookup (uniform test)
-            const int32_t* rp = a.inj.row_ptr;
-            if (rp[(x + 1) * ny] != rp[x * ny] && own) {
-                const int64_t row = x * ny + y;
-                const int32_t e0 = rp[row], e1 = rp[row + 1];
-                float acc[VZ];
-                bool hit[VZ];
-#pragma unroll
-                for (int v = 0; v < VZ; ++v) { acc[v] = 0.f; hit[v] = false; }
-                for (int32_t e = e0; e < e1; ++e) {
-                    const InjEntry en = a.inj.ent[e];
-                    const int64_t dz = (int64_t)en.z - z;
-#pragma unroll
-                    for (int v = 0; v < VZ; ++v)
-                        if (dz == v) {
-                            acc[v] = fmaf(en.w, a.inj_val[en.pt], acc[v]);
-                            hit[v] = true;
-                        }
-                }
-#pragma unroll
-                for (int v = 0; v < VZ; ++v)
-                    if (hit[v]) o[v] = fmaf(P.al[v], acc[v], o[v]);
-            }
-        }
+        if (inj_any && P.e1 > P.e0) inject_entries<VZ>(a, P.e0, P.e1, z, P.al, o);
         if (own) {
             const int64_t off = x * sx + col;
             if constexpr (IMG) {
@@ -478,6 +501,7 @@ __device__ __forceinline__ void slab_body(const StepArgs& a, int64_t L)
     constexpr int NT = T::NT, TZ = T::TZ, RZ = T::RZ, PITCH = T::PITCH;
     constexpr int XR = kSlabRows, ROWS = XR + 2 * R, NV = PITCH / VZ, RPT = XR / TW;
     static_assert(XR % TW == 0, "rows per wave must be whole");
+    static_assert(XR <= 64, "the injection rows of a chunk are one wave-wide ballot");
     static_assert(TZL % 64 == 0, "one wave per row group keeps the row test uniform");
     __shared__ __attribute__((aligned(16))) float lds[ROWS * PITCH];
 
@@ -501,10 +525,26 @@ __device__ __forceinline__ void slab_body(const StepArgs& a, int64_t L)
         if (xx >= 0 && xx < nx && zz >= 0 && zz < nz) v = vload<VZ>(u + xx * nz + zz);
         vstore<VZ>(lds + r * PITCH + k * VZ, v);
     }
+    // rows of the chunk holding injected nodes: one flag per lane, one ballot
+    // (a chunk has at most 64 rows), then each lane's entry range is fetched
+    // with its other per-row operands
+    const int32_t* rp = a.inj.row_ptr;
+    const bool inj_any = a.inj_val && xb > a.inj_x0 && xa <= a.inj_x1;
+    uint64_t inj_rows = 0;
+    if (inj_any) {
+        const int lane = tid & 63;
+        inj_rows = __ballot(lane < count && rp[xa + lane + 1] != rp[xa + lane]);
+    }
     Vec<VZ> uo[RPT], al[RPT], be[RPT], fw[RPT], gr[RPT];
+    int32_t e0[RPT], e1[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int r = tw + q * TW;
+        e0[q] = e1[q] = 0;
+        if (own && r < count && ((inj_rows >> r) & 1u)) {
+            e0[q] = rp[xa + r];
+            e1[q] = rp[xa + r + 1];
+        }
         uo[q] = al[q] = be[q] = fw[q] = gr[q] = vzero<VZ>();
         if (own && r < count) {
             const int64_t off = (xa + r) * nz + z;
@@ -521,7 +561,6 @@ __device__ __forceinline__ void slab_body(const StepArgs& a, int64_t L)
     }
     __syncthreads();
 
-    const bool inj_any = a.inj_val && a.inj.row_ptr[xb] != a.inj.row_ptr[xa];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int r = tw + q * TW;
@@ -543,7 +582,7 @@ __device__ __forceinline__ void slab_body(const StepArgs& a, int64_t L)
             for (int v = 0; v < VZ; ++v) lap[v] = fmaf(a.cx[j], (p[v] + m[v]) + m2c[v], lap[v]);
         }
         z_terms<R, VZ, RZ>(Lc, c, m2c, a.cz, lap);
-        const Vec<VZ> o = update_inject<VZ>(a, c, lap, uo[q], al[q], be[q], inj_any, own, x, 0, z);
+        const Vec<VZ> o = update_inject<VZ>(a, c, lap, uo[q], al[q], be[q], e0[q], e1[q], z);
         if (own) {
             const int64_t off = x * nz + z;
             if constexpr (IMG) {
@@ -567,15 +606,28 @@ __device__ __forceinline__ void stream_tile(const StepArgs& a, int64_t L)
     else stream_body<DIM, R, VZ, TZL, TY, IMG>(a, L);
 }
 
-// Single shot: the first blocks are tiles, the rest sample receivers.  With
+// Single shot: the first blocks are tiles, the last `sample_blocks` sample
+// the receivers (they only read `cur`).  Placed first instead, they took
+// resident slots from the tiles and pushed a share of them into a further
+// partial round (512^3 order 16: 523 us against 488 us per step).  With
 // `remap` the tile part of the grid is padded to a multiple of 8 and block b
 // takes tile L = (b mod 8) * (part / 8) + b / 8: blocks are dealt to the 8
 // XCDs in turn, so each XCD gets a contiguous run of tiles, and neighbouring
 // tiles and chunks, which read each other's halo, share one L2.  (2001 x 801
 // order 8 with 2D slabs: 6.5 us per step with 504 tiles, 10.0 us with 1004
 // tiles before the padding, which then ran without the remap.)
+// Waves per SIMD the plain 3D step asks the compiler to keep resident (the
+// second launch bound): 3 with four z-points per lane, 4 with two.  At order
+// 16 the 64 z x 16 tile otherwise takes 169 VGPRs, one above what 3 waves
+// per SIMD allow, and runs at 2.  The imaging step is left to the compiler.
+template <int DIM, int VZ, bool IMG>
+constexpr int step_waves_per_eu()
+{
+    return (DIM == 3 && !IMG) ? (VZ == 4 ? 3 : 4) : 1;
+}
+
 template <int DIM, int R, int VZ, int TZL, int TY, bool IMG>
-__global__ __launch_bounds__(TZL* TY) void k_step_stream(StepArgs a)
+__global__ __launch_bounds__(TZL* TY, (step_waves_per_eu<DIM, VZ, IMG>())) void k_step_stream(StepArgs a)
 {
     const int64_t b = blockIdx.x;
     const int64_t SB = a.stencil_blocks;
@@ -732,6 +784,11 @@ hipError_t with_shape(int variant, int64_t nz, F&& f)
         case 3: return f(ShapeCfg<3, R, 3>{});
         case 4: return f(ShapeCfg<3, R, 4>{});
         case 5: return f(ShapeCfg<3, R, 5>{});
+        case 6: return f(ShapeCfg<3, R, 6>{});
+        case 7: return f(ShapeCfg<3, R, 7>{});
+        case 8: return f(ShapeCfg<3, R, 8>{});
+        case 9: return f(ShapeCfg<3, R, 9>{});
+        case 10: return f(ShapeCfg<3, R, 10>{});
         default: return hipErrorInvalidValue;
         }
     }
@@ -759,9 +816,11 @@ int64_t plan_t(StepArgs& a, int xchunk, int64_t resident = 0, bool single = fals
         if (C::DIM == 3) {
             int64_t want = resident > 0 ? resident : (C::R <= 6 ? 1024 : 2048);
             // two-point lanes: a block is half the work of a four-point one
-            // at the same rows; two rounds of them measured fastest (256^3
-            // order 8: 52.2 us at 16-plane chunks against 53.5 us at 32)
-            if (C::VZ == 2) want *= 2;
+            // at the same rows; up to order 12 two rounds of them measured
+            // fastest (256^3 order 8: 52.2 us at 16-plane chunks against
+            // 53.5 us at 32), at order 16 one round (512^3: 470 us at 256
+            // planes against 508 us at 128)
+            if (C::VZ == 2 && C::R <= 6) want *= 2;
             int64_t chunks = want / tiles;
             if (chunks < 1) chunks = 1;
             xc = (a.nx + chunks - 1) / chunks;
@@ -836,12 +895,23 @@ hipError_t persistent_grid(K kern, int nt_block, int64_t items, int* grid)
 
 }  // namespace
 
+// Blocks of the step kernel of config CC (plain or imaging) resident on the
+// device at once, cached per kernel (0 when the runtime cannot say).
+template <class CC, bool IMG>
+int64_t step_resident()
+{
+    static std::atomic<int64_t> cache{-1};
+    return resident_blocks(k_step_stream<CC::DIM, CC::R, CC::VZ, CC::TZL, CC::TY, IMG>, CC::T::NT, cache);
+}
+
 template <int O>
-int64_t OrderOps<O>::plan(int ndim, TileCfg cfg, StepArgs& a)
+int64_t OrderOps<O>::plan(int ndim, TileCfg cfg, StepArgs& a, bool device)
 {
     int64_t blocks = -1;
     auto f = [&](auto C) {
-        blocks = plan_t<decltype(C)>(a, cfg.xchunk);
+        using CC = decltype(C);
+        const int64_t res = (device && cfg.xchunk <= 0) ? step_resident<CC, false>() : 0;
+        blocks = plan_t<CC>(a, cfg.xchunk, res, device);
         return hipSuccess;
     };
     (void)(ndim == 2 ? with_shape<2, O / 2>(cfg.variant, a.nz, f) : with_shape<3, O / 2>(cfg.variant, a.nz, f));
@@ -853,18 +923,18 @@ hipError_t OrderOps<O>::step(int ndim, const StepArgs& a0, hipStream_t s, TileCf
 {
     auto f = [&](auto C) {
         using CC = decltype(C);
-        auto launch = [&](auto kern, std::atomic<int64_t>& cache) {
+        auto launch = [&](auto kern, int64_t res) {
             StepArgs a = a0;
-            const int64_t res = cfg.xchunk <= 0 ? resident_blocks(kern, CC::T::NT, cache) : 0;
             const int64_t blocks = plan_t<CC>(a, cfg.xchunk, res, true);
             if (!(a.smp_out && a.smp.npts > 0)) a.smp.npts = 0;
             hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(CC::T::NT), 0, s, a);
             return hipGetLastError();
         };
-        static std::atomic<int64_t> res_img{-1}, res_plain{-1};
         if (a0.img_grad)
-            return launch(k_step_stream<CC::DIM, CC::R, CC::VZ, CC::TZL, CC::TY, true>, res_img);
-        return launch(k_step_stream<CC::DIM, CC::R, CC::VZ, CC::TZL, CC::TY, false>, res_plain);
+            return launch(k_step_stream<CC::DIM, CC::R, CC::VZ, CC::TZL, CC::TY, true>,
+                          cfg.xchunk <= 0 ? step_resident<CC, true>() : 0);
+        return launch(k_step_stream<CC::DIM, CC::R, CC::VZ, CC::TZL, CC::TY, false>,
+                      cfg.xchunk <= 0 ? step_resident<CC, false>() : 0);
     };
     return ndim == 2 ? with_shape<2, O / 2>(cfg.variant, a0.nz, f) : with_shape<3, O / 2>(cfg.variant, a0.nz, f);
 }

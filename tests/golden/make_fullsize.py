@@ -6,7 +6,11 @@ Runs the FP64 oracle (and nothing else) on the seeded 256^3 workload for all
   d        oracle traces at those receivers [1000][len(rec_idx)]
   pts      sampled flat grid indices
   u        oracle u^1000 at those points
-Usage: python tests/golden/make_fullsize.py   (about 5 minutes on 8 cores)
+and, after a second pass with --precision f32, the error of the FP32 build of
+the oracle against those values (f32_rel_d, f32_rel_u, f32_maxrel_d,
+f32_maxrel_u): the FP32 round-off floor of the plain scheme.
+Usage: python tests/golden/make_fullsize.py [--precision f32]
+(about 5 minutes per pass on 8 cores)
 """
 import os
 import sys
@@ -34,12 +38,36 @@ def sample_indices(p):
     return rec_idx, pts
 
 
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def maxrel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
 def main():
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--precision", choices=("f64", "f32"), default="f64",
+                    help="f64 writes the reference; f32 then adds the error of the FP32 build "
+                         "of the oracle at the same samples (f32_rel_d, f32_rel_u, "
+                         "f32_maxrel_d, f32_maxrel_u)")
+    args = ap.parse_args()
     p = synth.config_3d_o8()
     rec_idx, pts = sample_indices(p)
-    r = oracle.forward(p.shape, p.spacing, p.order, p.dt, p.nt, p.m, p.eta, p.src, p.q, p.rec)
-    np.savez_compressed(OUT, rec_idx=rec_idx, d=r["d"][:, rec_idx], pts=pts,
-                        u=r["u"].ravel()[pts])
+    r = oracle.forward(p.shape, p.spacing, p.order, p.dt, p.nt, p.m, p.eta, p.src, p.q, p.rec,
+                       precision=args.precision)
+    d, u = r["d"][:, rec_idx], r["u"].ravel()[pts]
+    if args.precision == "f64":
+        np.savez_compressed(OUT, rec_idx=rec_idx, d=d, pts=pts, u=u)
+    else:
+        g = dict(np.load(OUT))
+        assert np.array_equal(g["pts"], pts) and np.array_equal(g["rec_idx"], rec_idx)
+        g["f32_rel_d"], g["f32_maxrel_d"] = rel(d, g["d"]), maxrel(d, g["d"])
+        g["f32_rel_u"], g["f32_maxrel_u"] = rel(u, g["u"]), maxrel(u, g["u"])
+        print({k: float(g[k]) for k in g if k.startswith("f32_")}, flush=True)
+        np.savez_compressed(OUT, **g)
     print("wrote", OUT)
 
 

@@ -95,12 +95,12 @@ def test_forward_argument_errors_return_before_any_device_work():
     assert _forward_rc(ws=False) == L.WAVE_EWORKSPACE
     assert _forward_rc(ws_bytes=1024) == L.WAVE_EWORKSPACE
     assert b"workspace" in L.lib().wave_last_error()
-    # block shapes: 4 in 2D (ids 0..3), 6 in 3D (ids 0..5)
+    # block shapes: 4 in 2D (ids 0..3), 11 in 3D (ids 0..10)
     assert _forward_rc(tile=(4 << 16) | 8) == L.WAVE_EINVAL
     assert b"variant 4" in L.lib().wave_last_error()
     assert _forward_rc(tile=-1) == L.WAVE_EINVAL
     assert _forward_rc(shape=(20, 30, 40), src=((50.0, 50.0, 50.0),), rec=((10.0, 20.0, 30.0),),
-                       tile=(6 << 16) | 8) == L.WAVE_EINVAL
+                       tile=(11 << 16) | 8) == L.WAVE_EINVAL
 
 
 def test_library_fields_use_rows_padded_to_four_points():

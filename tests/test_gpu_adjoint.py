@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import device_inputs, rel_l2
+from gpu_util import assert_close, device_inputs, record, rel_l2
 from paper_1609_03361_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -30,8 +30,8 @@ def test_adjoint_matches_oracle(dev, shape, order):
     qa, v0 = api.adjoint(geom, m, eta, torch.from_numpy(dres).to(dev), return_final=True)
     torch.cuda.synchronize()
     ref = oracle.adjoint(p.shape, p.spacing, p.order, p.dt, p.nt, p.m, p.eta, p.rec, dres, p.src)
-    assert rel_l2(qa.cpu().numpy(), ref["qadj"]) < 1e-5
-    assert rel_l2(v0.cpu().numpy(), ref["v"]) < 1e-5
+    assert_close(qa.cpu().numpy(), ref["qadj"], f"adjoint {p.name} q_adj")
+    assert_close(v0.cpu().numpy(), ref["v"], f"adjoint {p.name} v^0")
 
 
 @pytest.mark.parametrize("shape,order", [((60, 70), 8), ((30, 28, 33), 4), ((26, 30, 31), 16)])
@@ -54,6 +54,29 @@ def test_dot_product_fp32(dev, shape, order):
     print(f"dot {p.name}: {lhs!r} {rhs!r} ratio-1 {lhs / rhs - 1:.2e} "
           f"normalised {abs(lhs - rhs) / scale:.2e}", flush=True)
     assert abs(lhs - rhs) <= 1e-6 * scale
+
+
+@pytest.mark.parametrize("shape,order", [((60, 70), 8), ((30, 28, 33), 4), ((26, 30, 31), 16)])
+def test_dot_product_ratio_fp32(dev, shape, order):
+    """The adjoint test of the paper (equation eqn:adjtest) in its plain ratio
+    form, on a well-conditioned pair: y = F x + noise (10 % of |F x|), so that
+    <F x, y> does not cancel; |1 - <F x, y> / <x, F^T y>| <= 1e-5."""
+    import torch
+    from paper_1609_03361_amd import api
+    p = synth.random_problem(shape, order, 60, seed=5 * order, nsrc=4, nrec=15)
+    geom, m, eta, q = device_inputs(p, dev)
+    Fx = api.forward(geom, m, eta, q)
+    rng = np.random.default_rng(7)
+    noise = torch.from_numpy(rng.standard_normal(tuple(Fx.shape)).astype(np.float32)).to(dev)
+    y = (Fx + 0.1 * float(Fx.norm()) / float(noise.norm()) * noise).contiguous()
+    FTy = api.adjoint(geom, m, eta, y)
+    torch.cuda.synchronize()
+    lhs = float((Fx.double() * y.double()).sum())
+    rhs = float((q.double() * FTy.double()).sum())
+    ratio = abs(1.0 - lhs / rhs)
+    print(f"dot ratio {p.name}: <Fx,y> {lhs!r} <x,F^T y> {rhs!r} |1 - ratio| {ratio:.2e}", flush=True)
+    record(f"dot ratio {p.name}", ratio_err=ratio, tol=1e-5)
+    assert ratio <= 1e-5
 
 
 def _gradient_case(shape, order, nt, seed=21):
@@ -80,15 +103,21 @@ def test_gradient_matches_oracle(dev, shape, order, nt, every):
     torch.cuda.synchronize()
     ref = oracle.gradient(p.shape, p.spacing, p.order, p.dt, p.nt, p.m, p.eta, p.src, p.q, p.rec,
                           d_obs)
+    r32 = oracle.gradient(p.shape, p.spacing, p.order, p.dt, p.nt, p.m, p.eta, p.src, p.q, p.rec,
+                          d_obs, precision="f32")
+    floor = rel_l2(r32["grad"], ref["grad"])
     eg = rel_l2(g.cpu().numpy(), ref["grad"])
     # J = 1/2 |d - d_obs|^2: an FP32 error dd in the traces moves J by about
     # <r, dd>, so the misfit is held to 1e-5 |r| |d| rather than 1e-5 J
     r_ref = ref["d"] - d_obs
     bound = 1e-5 * np.linalg.norm(r_ref) * np.linalg.norm(ref["d"])
     ej = abs(float(J) - ref["J"])
-    print(f"gradient rel L2 {eg:.2e}  misfit rel {ej / ref['J']:.2e} "
+    print(f"gradient rel L2 {eg:.2e} (FP32 oracle {floor:.2e})  misfit rel {ej / ref['J']:.2e} "
           f"(bound {bound / ref['J']:.2e})", flush=True)
+    record(f"gradient {p.name} every={every}", rel_l2=eg, fp32_oracle=floor,
+           misfit_rel=ej / ref["J"])
     assert eg < 1e-4
+    assert eg <= 2 * floor
     assert ej <= bound
 
 

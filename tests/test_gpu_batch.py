@@ -89,8 +89,8 @@ def test_tiles_do_not_change_results(dev, shape, order):
     p = synth.random_problem(shape, order, 16, seed=5, nsrc=3, nrec=8)
     geom, m, eta, q = device_inputs(p, dev)
     ref = api.forward(geom, m, eta, q, return_final=True)
-    # block shapes: 4 in 2D, 6 in 3D (rows are padded to 4 points inside the library)
-    for v in range(4 if len(shape) == 2 else 6):
+    # block shapes: 4 in 2D, 11 in 3D (rows are padded to 4 points inside the library)
+    for v in range(4 if len(shape) == 2 else 11):
         for x in (1, order // 2, 7, 64):
             got = api.forward(geom, m, eta, q, return_final=True, tile=api.tile_id(v, x))
             torch.cuda.synchronize()

@@ -1,10 +1,12 @@
 """Forward parity: the HIP path (through the C ABI) against the FP64 oracle
-on the same seeded inputs.  Tolerance: relative L2 <= 1e-5 on the traces
-and on the final wavefield."""
+on the same seeded inputs.  Tolerance: relative L2 <= 1e-5 and max-abs /
+max-ref <= 1e-5 on the traces and on the final wavefield.  On the 101^2
+order-4 workload the FP32 build of the oracle is run too: the GPU error must
+stay within twice that FP32 round-off floor."""
 import numpy as np
 import pytest
 
-from gpu_util import device_inputs, oracle_forward, rel_l2
+from gpu_util import assert_close, device_inputs, oracle_forward, record, rel_l2
 from paper_1609_03361_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -32,8 +34,12 @@ def test_2d_101_order4_full(dev):
     print(f"case {p.name} nt={p.nt}", flush=True)
     d, u = _run(p, dev)
     ref = oracle_forward(p)
-    assert rel_l2(d, ref["d"]) < TOL
-    assert rel_l2(u, ref["u"]) < TOL
+    r32 = oracle_forward(p, precision="f32")
+    floor_d, floor_u = rel_l2(r32["d"], ref["d"]), rel_l2(r32["u"], ref["u"])
+    ed, _ = assert_close(d, ref["d"], f"{p.name} traces", fp32_oracle=floor_d)
+    eu, _ = assert_close(u, ref["u"], f"{p.name} u^nt", fp32_oracle=floor_u)
+    print(f"FP32 oracle floor: traces {floor_d:.3e}, u {floor_u:.3e}", flush=True)
+    assert ed <= 2 * floor_d and eu <= 2 * floor_u
 
 
 SWEEP = [((37, 29), 2, 40), ((61, 70), 4, 50), ((45, 131), 6, 40), ((33, 65), 8, 60),
@@ -49,8 +55,8 @@ def test_random_sweep(dev, shape, order, nt):
     print(f"case {p.name}", flush=True)
     d, u = _run(p, dev)
     ref = oracle_forward(p)
-    assert rel_l2(d, ref["d"]) < TOL, rel_l2(d, ref["d"])
-    assert rel_l2(u, ref["u"]) < TOL, rel_l2(u, ref["u"])
+    assert_close(d, ref["d"], f"{p.name} traces")
+    assert_close(u, ref["u"], f"{p.name} u^nt")
 
 
 def test_3d_64_order8_200_steps(dev):
@@ -58,8 +64,8 @@ def test_3d_64_order8_200_steps(dev):
     print(f"case {p.name}", flush=True)
     d, u = _run(p, dev)
     ref = oracle_forward(p)
-    assert rel_l2(d, ref["d"]) < TOL, rel_l2(d, ref["d"])
-    assert rel_l2(u, ref["u"]) < TOL, rel_l2(u, ref["u"])
+    assert_close(d, ref["d"], f"{p.name} traces")
+    assert_close(u, ref["u"], f"{p.name} u^nt")
 
 
 def test_no_sources_no_receivers_and_zero_field(dev):

@@ -15,7 +15,7 @@ import os
 import numpy as np
 import pytest
 
-from gpu_util import rel_l2
+from gpu_util import assert_close, rel_l2
 from paper_1609_03361_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -30,10 +30,11 @@ def dev():
 
 
 def test_48_batched_shots_full_size_sampled(dev):
-    """Measured 8.9e-6, 9.7e-6 and 4.3e-6: over 2000 steps the FP32 rounding of
-    each update adds up like a random walk (1000 steps of 256^3 give 1.7e-6,
-    20 steps 1.5e-7), so the widest shots sit close to the 1e-5 bound.  The
-    result is bitwise reproducible and does not depend on the tile."""
+    """Three of the shots (the first, the narrowest, the widest) at sampled
+    times and receivers: relative L2 and max-abs / max-ref <= 1e-5, and within
+    twice the error of the FP32 build of the oracle on the same samples (stored
+    with the reference).  Over 2000 steps the FP32 rounding of each update adds
+    up; the results are bitwise reproducible and do not depend on the tile."""
     import torch
     from paper_1609_03361_amd import api
     ref = np.load(GOLD)
@@ -45,10 +46,11 @@ def test_48_batched_shots_full_size_sampled(dev):
     torch.cuda.synchronize()
     for k, s in enumerate(ref["shots"]):
         got = d[int(s)].cpu().numpy()[np.ix_(ref["t_idx"], ref["rec_idx"])]
-        e = rel_l2(got, ref["d"][k])
-        print(f"batched shot {int(s)} ({probs[int(s)].name}): sampled traces rel L2 {e:.2e}",
-              flush=True)
-        assert e < 1e-5
+        floor = float(ref["f32_rel"][k])
+        e, _ = assert_close(got, ref["d"][k], f"batched shot {int(s)} ({probs[int(s)].name}) "
+                            f"sampled traces", fp32_oracle=floor)
+        print(f"  FP32 oracle at the same samples: {floor:.3e}", flush=True)
+        assert e <= 2 * floor
 
 
 @pytest.mark.parametrize("ckpt_dtype", ["fp32", "bf16"])

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import rel_l2
+from gpu_util import record, rel_l2
 from paper_1609_03361_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -24,18 +24,21 @@ ADDED = {"fp16": 2e-4, "bf16": 2e-3}
 @pytest.fixture(scope="module")
 def case():
     m0, m_true, eta, shots = synth.config_gradient_3d(n=48, nt=1500, width=10, nrec_side=24)
-    d_obs, g_ref, J_ref, dn, rn = [], np.zeros(m0.shape), 0.0, 0.0, 0.0
+    d_obs, g_ref, g_f32, J_ref, dn, rn = [], np.zeros(m0.shape), np.zeros(m0.shape), 0.0, 0.0, 0.0
     for p in shots:
         print(f"oracle shot {p.name}", flush=True)
         d = oracle.forward(p.shape, p.spacing, p.order, p.dt, p.nt, m_true, eta, p.src, p.q,
                            p.rec, want_final=False)["d"].astype(np.float32)
         r = oracle.gradient(p.shape, p.spacing, p.order, p.dt, p.nt, m0, eta, p.src, p.q, p.rec, d)
+        r32 = oracle.gradient(p.shape, p.spacing, p.order, p.dt, p.nt, m0, eta, p.src, p.q, p.rec,
+                              d, precision="f32")
         d_obs.append(d)
         g_ref += r["grad"]
+        g_f32 += r32["grad"]
         J_ref += r["J"]
         dn += float(np.sum(r["d"] ** 2))
         rn += float(np.sum((r["d"] - d) ** 2))
-    return m0, eta, shots, d_obs, g_ref, J_ref, math.sqrt(dn / rn)
+    return m0, eta, shots, d_obs, g_ref, J_ref, math.sqrt(dn / rn), rel_l2(g_f32, g_ref)
 
 
 def _gpu_gradient(case, dtype):
@@ -58,19 +61,27 @@ def _gpu_gradient(case, dtype):
 
 
 def test_gradient_48cube_vs_oracle(case):
-    g_ref, J_ref, amp = case[4], case[5], case[6]
+    """FP32 / FP16 / BF16 checkpoints: gradient error against the FP64 oracle,
+    beside the error of the FP32 build of the oracle (the FP32 floor of the
+    plain scheme): the GPU's FP32 path must stay within twice that floor."""
+    g_ref, J_ref, amp, floor = case[4], case[5], case[6], case[7]
     bound = 1e-5 * amp
     g32, J32 = _gpu_gradient(case, "fp32")
     err = rel_l2(g32, g_ref)
     print(f"48^3 x 4 shots |d|/|r| = {amp:.1f}; FP32 checkpoints: gradient rel L2 {err:.3e} "
-          f"(bound {bound:.2e}), misfit rel {abs(J32 - J_ref) / J_ref:.3e}", flush=True)
+          f"(bound {bound:.2e}, FP32 oracle {floor:.3e}), misfit rel {abs(J32 - J_ref) / J_ref:.3e}",
+          flush=True)
+    record("gradient 48^3 x 4 shots fp32", rel_l2=err, fp32_oracle=floor, bound=bound,
+           misfit_rel=abs(J32 - J_ref) / J_ref)
     assert err < bound
+    assert err <= 2 * floor
     for dtype in ("fp16", "bf16"):
         g, J = _gpu_gradient(case, dtype)
         e_ref = rel_l2(g, g_ref)
         added = rel_l2(g, g32)
         print(f"{dtype} checkpoints: gradient rel L2 vs oracle {e_ref:.3e}, added by the "
               f"checkpoint rounding {added:.3e}", flush=True)
+        record(f"gradient 48^3 x 4 shots {dtype}", rel_l2=e_ref, added=added, fp32_oracle=floor)
         assert e_ref < bound
         assert added < ADDED[dtype]
 

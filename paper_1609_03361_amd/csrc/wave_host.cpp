@@ -292,8 +292,12 @@ struct HostInject {
 void make_inject(const Geo& G, const HostPoints& P, HostInject* out)
 {
     const int d = G.ndim, nc = 1 << d;
-    out->ent.clear();
-    out->ent.reserve((size_t)P.npts * nc);
+    struct Keyed {
+        int32_t row;
+        InjEntry e;
+    };
+    std::vector<Keyed> ent;
+    ent.reserve((size_t)P.npts * nc);
     for (int p = 0; p < P.npts; ++p) {
         const int64_t* i0 = &P.cell[(size_t)p * 3];
         for (int c = 0; c < nc; ++c) {
@@ -303,23 +307,27 @@ void make_inject(const Geo& G, const HostPoints& P, HostInject* out)
             } else {
                 idx[0] += (c >> 1) & 1; idx[2] += c & 1;
             }
-            InjEntry e;
-            e.row = (int32_t)(idx[0] * G.n[1] + idx[1]);
-            e.z = (int32_t)idx[2];
-            e.pt = p;
-            e.w = P.w[(size_t)p * nc + c];
-            out->ent.push_back(e);
+            Keyed k;
+            k.row = (int32_t)(idx[0] * G.n[1] + idx[1]);
+            k.e.z = (int32_t)idx[2];
+            k.e.pt = p;
+            k.e.w = P.w[(size_t)p * nc + c];
+            ent.push_back(k);
         }
     }
     // (row, z, point) is a total order: two corners of one point never share a node
-    std::sort(out->ent.begin(), out->ent.end(), [](const InjEntry& a, const InjEntry& b) {
+    std::sort(ent.begin(), ent.end(), [](const Keyed& a, const Keyed& b) {
         if (a.row != b.row) return a.row < b.row;
-        if (a.z != b.z) return a.z < b.z;
-        return a.pt < b.pt;
+        if (a.e.z != b.e.z) return a.e.z < b.e.z;
+        return a.e.pt < b.e.pt;
     });
     const int64_t nrows = G.nrows();
     out->row_ptr.assign(nrows + 1, 0);
-    for (const InjEntry& e : out->ent) out->row_ptr[e.row + 1]++;
+    out->ent.resize(ent.size());
+    for (size_t i = 0; i < ent.size(); ++i) {
+        out->row_ptr[ent[i].row + 1]++;
+        out->ent[i] = ent[i].e;
+    }
     for (int64_t r = 0; r < nrows; ++r) out->row_ptr[r + 1] += out->row_ptr[r];
 }
 
@@ -336,8 +344,17 @@ struct Plan {
     size_t adj[2] = {0, 0};                 // adjoint wavefield pair
     size_t resid = 0, dsyn = 0, red = 0;    // gradient: residual, modelled data, reduction
     size_t ckpt = 0;                        // gradient: checkpoint storage
+    // injection values gathered into entry order, double-buffered, for
+    // point sets of at least kDenseEntries entries: [0] sources, [1] receivers
+    size_t ev[2][2] = {{0, 0}, {0, 0}};
     size_t total = 0;
 };
+
+// Injected point sets with this many entries (2^d per point) or more have
+// their values gathered into entry order one step ahead, by extra blocks of
+// the previous launch: the owner's lookup then costs one memory round trip
+// instead of two.  Sparser sets (a few sources) read the values directly.
+constexpr int kDenseEntries = 256;
 
 struct Carver {
     size_t off = 0;
@@ -421,6 +438,10 @@ Plan make_plan(int op, const Geo& G, int nsrc, int nrec, const wave_opts* o)
         P.ring = c.take(N * 4);
         P.gacc = c.take(N * 4);
     }
+    const int nent[2] = {fwd ? nsrc * nc : 0, adj ? nrec * nc : 0};
+    for (int s = 0; s < 2; ++s)
+        if (nent[s] >= kDenseEntries)
+            for (int b = 0; b < 2; ++b) P.ev[s][b] = c.take((size_t)nent[s] * 4);
     if (op == WAVE_OP_GRADIENT || op == WAVE_OP_FORWARD_CKPT) P.red = c.take(kRedFloats * 4);
     if (op == WAVE_OP_GRADIENT) {
         P.resid = c.take((size_t)G.nt * nrec * 4);
@@ -710,6 +731,27 @@ void bind_sparse(const Ctx& C, StepArgs& a, int set)
     a.smp.npts = set == 0 ? C.rec.npts : C.src.npts;
 }
 
+// Gathered injection for one step: `set` 0 = sources, 1 = receivers; step
+// `n` reads the buffer of parity n and, when `next_vals` is given, the launch
+// gathers the next step's values into the other buffer.  No-op for sparse sets.
+void gathered(const Ctx& C, StepArgs& a, int set, int n, const float* next_vals)
+{
+    if (!C.P.ev[set][0]) return;
+    const int nent = (set == 0 ? C.src.npts : C.rec.npts) << C.G.ndim;
+    a.inj_ev = C.at<float>(C.P.ev[set][n & 1]);
+    a.ev_out = next_vals ? C.at<float>(C.P.ev[set][(n + 1) & 1]) : nullptr;
+    a.ev_src = next_vals;
+    a.nent = next_vals ? nent : 0;
+}
+
+// The first gathered step's values (parity of step n).
+hipError_t gather_first(const Ctx& C, const StepArgs& a, int set, int n, const float* vals)
+{
+    if (!C.P.ev[set][0]) return hipSuccess;
+    const int nent = (set == 0 ? C.src.npts : C.rec.npts) << C.G.ndim;
+    return launch_gather(C.at<float>(C.P.ev[set][n & 1]), vals, a.inj.ent, nent, C.s);
+}
+
 hipError_t step(const Ctx& C, const StepArgs& a)
 {
     ++TS().prof.launches;
@@ -782,6 +824,7 @@ int run_forward(const Ctx& C, const float* q, float* d, float* u_final, const Ck
     HIP_TRY(launch_fill(buf[1], N, 0.f, C.s));
     StepArgs a = base_args(C);
     bind_sparse(C, a, 0);
+    if (C.src.npts) HIP_TRY(gather_first(C, a, 0, 0, q));
     int cur = 0;   // buf[cur] = u^n, buf[1-cur] = u^{n-1}
     if (prof_begin(C.s)) return fail(WAVE_EHIP, "profiling event failed");
     for (int n = 0; n < C.G.nt; ++n) {
@@ -793,6 +836,8 @@ int run_forward(const Ctx& C, const float* q, float* d, float* u_final, const Ck
         a.other = buf[1 - cur];
         a.out = buf[1 - cur];
         a.inj_val = C.src.npts ? q + (size_t)n * C.src.npts : nullptr;
+        if (C.src.npts)
+            gathered(C, a, 0, n, n + 1 < C.G.nt ? q + (size_t)(n + 1) * C.src.npts : nullptr);
         a.smp_out = C.rec.npts ? d + (size_t)n * C.rec.npts : nullptr;
         HIP_TRY(step(C, a));
         cur = 1 - cur;
@@ -823,6 +868,7 @@ int run_backward(const Ctx& C, const float* q, const float* r, const CkptView& c
     StepArgs ba = base_args(C);
     bind_sparse(C, ba, 1);
     ba.img_grad = gacc;
+    if (C.rec.npts) HIP_TRY(gather_first(C, ba, 1, nt - 1, r + (size_t)(nt - 1) * C.rec.npts));
     int vc = 0;    // v[vc] = v^k, v[1-vc] = v^{k+1}
     if (open_prof && prof_begin(C.s)) return fail(WAVE_EHIP, "profiling event failed");
     for (int seg = ck.nck - 1; seg >= 0; --seg) {
@@ -843,6 +889,7 @@ int run_backward(const Ctx& C, const float* q, const float* r, const CkptView& c
             ba.other = v[1 - vc];
             ba.out = v[1 - vc];
             ba.inj_val = C.rec.npts ? r + (size_t)k * C.rec.npts : nullptr;
+            if (C.rec.npts) gathered(C, ba, 1, k, k > 0 ? r + (size_t)(k - 1) * C.rec.npts : nullptr);
             ba.smp_out = (grad_q && C.src.npts) ? grad_q + (size_t)k * C.src.npts : nullptr;
             ba.img_fwd = slot(k - c0 + 1);
             HIP_TRY(step(C, ba));
@@ -1430,6 +1477,7 @@ int wave_adjoint(const wave_grid* grid, const float* m, const float* eta, const 
         HIP_TRY(launch_fill(v[1], N, 0.f, C.s));
         StepArgs a = base_args(C);
         bind_sparse(C, a, 1);
+        if (C.rec.npts) HIP_TRY(gather_first(C, a, 1, C.G.nt - 1, d + (size_t)(C.G.nt - 1) * C.rec.npts));
         int vc = 0;
         if (prof_begin(C.s)) return fail(WAVE_EHIP, "profiling event failed");
         for (int k = C.G.nt - 1; k >= 0; --k) {
@@ -1437,6 +1485,7 @@ int wave_adjoint(const wave_grid* grid, const float* m, const float* eta, const 
             a.other = v[1 - vc];
             a.out = v[1 - vc];
             a.inj_val = C.rec.npts ? d + (size_t)k * C.rec.npts : nullptr;
+            if (C.rec.npts) gathered(C, a, 1, k, k > 0 ? d + (size_t)(k - 1) * C.rec.npts : nullptr);
             a.smp_out = C.src.npts ? q_adj + (size_t)k * C.src.npts : nullptr;
             HIP_TRY(step(C, a));
             vc = 1 - vc;

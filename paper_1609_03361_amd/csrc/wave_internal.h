@@ -9,14 +9,14 @@ namespace wave {
 
 constexpr int kMaxHalf = 8;        // space order 16 -> half-width 8
 
-// One injection contribution, sorted by (row, z, point): the owner of grid
-// node (row, z) adds alpha * w * val[pt] to its update.  row = x*ny + y (3D)
-// or x (2D).
+// One injection contribution.  Entries are sorted by (row, z, point) and a
+// per-row CSR gives each row's range: the owner of grid node (row, z) adds
+// alpha * w * val[pt] to its update, row = x*ny + y (3D) or x (2D).  Twelve
+// bytes (the row is implied by the CSR), one dwordx3 load.
 struct InjEntry {
     int32_t z;
     int32_t pt;
     float w;
-    int32_t row;
 };
 
 // Device view of a set of sparse points used for sampling: flat index of the
@@ -47,6 +47,15 @@ struct StepArgs {
     // injection into `out` (values for this step)
     InjectSet inj;
     const float* inj_val;  // [npts of the injected set] for this step, or nullptr
+    // optional: this step's weighted values already gathered into entry
+    // order, inj_ev[e] = ent[e].w * inj_val[ent[e].pt] (rounded product; the
+    // direct path forms the same product), or nullptr
+    const float* inj_ev;
+    // optional gather for the next step, done by extra blocks at the end of
+    // the launch: ev_out[e] = ent[e].w * ev_src[ent[e].pt] for e < nent
+    float* ev_out;
+    const float* ev_src;
+    int32_t nent;
     // sampling of `cur` (values for this step)
     SampleSet smp;
     float* smp_out;        // [npts] for this step, or nullptr
@@ -196,6 +205,9 @@ hipError_t launch_check_fields(const float* m, const float* eta, int64_t rows, i
                                int64_t nzp, float* partial, int nblocks, float* alpha, float* beta,
                                double dt, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
+// ev[e] = ent[e].w * val[ent[e].pt] for e < nent (the first step of a
+// gathered injection).
+hipError_t launch_gather(float* ev, const float* val, const InjEntry* ent, int32_t nent, hipStream_t s);
 // Diffusion coefficients alpha = dt a, beta = 0 and per block {max a, invalid count}
 // into `partial` (2 * nblocks floats); a is [rows][nz], alpha and beta [rows][nzp].
 hipError_t launch_diffusion_coef(const float* a, int64_t rows, int64_t nz, int64_t nzp,

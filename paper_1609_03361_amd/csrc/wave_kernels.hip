@@ -524,6 +524,20 @@ hipError_t launch_diffusion_coef(const float* a, int64_t rows, int64_t nz, int64
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(kBlock) void k_gather(float* __restrict__ ev, const float* __restrict__ val,
+                                                   const InjEntry* __restrict__ ent, int32_t nent)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e < nent) ev[e] = ent[e].w * val[ent[e].pt];
+}
+
+hipError_t launch_gather(float* ev, const float* val, const InjEntry* ent, int32_t nent, hipStream_t s)
+{
+    if (nent <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather, dim3((nent + kBlock - 1) / kBlock), dim3(kBlock), 0, s, ev, val, ent, nent);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;

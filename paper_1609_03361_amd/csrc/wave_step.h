@@ -198,11 +198,13 @@ __device__ __forceinline__ void inject_entries(const StepArgs& a, int32_t e0, in
     for (int v = 0; v < VZ; ++v) { acc[v] = 0.f; hit[v] = false; }
     for (int32_t e = e0; e < e1; ++e) {
         const InjEntry en = a.inj.ent[e];
+        // w * val rounded, then added: the gathered values hold the same products
+        const float wv = a.inj_ev ? a.inj_ev[e] : en.w * a.inj_val[en.pt];
         const int64_t dz = (int64_t)en.z - z;
 #pragma unroll
         for (int v = 0; v < VZ; ++v)
             if (dz == v) {
-                acc[v] = fmaf(en.w, a.inj_val[en.pt], acc[v]);
+                acc[v] = acc[v] + wv;
                 hit[v] = true;
             }
     }
@@ -393,6 +395,21 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, int64_t L)
         constexpr int B = U & 1;
         const int64_t x = x0 + dir * i;
         Pre& P = pre[U % PR];
+        // gathered injection: the depth and the value of the row's first two
+        // entries, loaded first (before the prefetch of later planes: loads
+        // complete in order, so waiting for these does not wait for those)
+        // and used after the stencil
+        const bool inj_here = inj_any && P.e1 > P.e0;
+        int32_t ez0 = -1, ez1 = -1;
+        float ev0 = 0.f, ev1 = 0.f;
+        if (inj_here && a.inj_ev) {
+            ez0 = a.inj.ent[P.e0].z;
+            ev0 = a.inj_ev[P.e0];
+            if (P.e0 + 1 < P.e1) {
+                ez1 = a.inj.ent[P.e0 + 1].z;
+                ev1 = a.inj_ev[P.e0 + 1];
+            }
+        }
         if (i + PR - 1 < count) fetch(pre[(U + PR - 1) % PR], x + dir * (PR - 1));
         Q[(U + 2 * R + 1) % S] = center(x + dir * (R + 1));
         float* Ls = lds[B];
@@ -460,7 +477,32 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, int64_t L)
             const float w = fmaf(P.be[v], c[v] - P.uo[v], c[v]);
             o[v] = fmaf(P.al[v], lap[v], w);
         }
-        if (inj_any && P.e1 > P.e0) inject_entries<VZ>(a, P.e0, P.e1, z, P.al, o);
+        if (inj_here) {
+            if (a.inj_ev) {
+                // same entries, same order as inject_entries
+                float acc[VZ];
+                bool hit[VZ];
+#pragma unroll
+                for (int v = 0; v < VZ; ++v) { acc[v] = 0.f; hit[v] = false; }
+#pragma unroll
+                for (int v = 0; v < VZ; ++v) {
+                    if (ez0 - z == v) { acc[v] = acc[v] + ev0; hit[v] = true; }
+                    if (ez1 >= 0 && ez1 - z == v) { acc[v] = acc[v] + ev1; hit[v] = true; }
+                }
+                for (int32_t e = P.e0 + 2; e < P.e1; ++e) {
+                    const int64_t dz = (int64_t)a.inj.ent[e].z - z;
+                    const float wv = a.inj_ev[e];
+#pragma unroll
+                    for (int v = 0; v < VZ; ++v)
+                        if (dz == v) { acc[v] = acc[v] + wv; hit[v] = true; }
+                }
+#pragma unroll
+                for (int v = 0; v < VZ; ++v)
+                    if (hit[v]) o[v] = fmaf(P.al[v], acc[v], o[v]);
+            } else {
+                inject_entries<VZ>(a, P.e0, P.e1, z, P.al, o);
+            }
+        }
         if (own) {
             const int64_t off = x * sx + col;
             if constexpr (IMG) {
@@ -633,8 +675,18 @@ __global__ __launch_bounds__(TZL* TY, (step_waves_per_eu<DIM, VZ, IMG>())) void 
     const int64_t SB = a.stencil_blocks;
     const int64_t part = a.remap ? (SB + 7) / 8 * 8 : SB;
     if (b >= part) {
-        const int64_t p = (b - part) * (TZL * TY) + threadIdx.x;
-        if (p < a.smp.npts) a.smp_out[p] = sample_point<DIM>(a.smp, a.cur, p, a.nz, a.ny * a.nz);
+        const int64_t nsb = a.smp_out && a.smp.npts > 0 ? (a.smp.npts + TZL * TY - 1) / (TZL * TY) : 0;
+        if (b - part < nsb) {
+            const int64_t p = (b - part) * (TZL * TY) + threadIdx.x;
+            if (p < a.smp.npts) a.smp_out[p] = sample_point<DIM>(a.smp, a.cur, p, a.nz, a.ny * a.nz);
+        } else {
+            // gather of the next step's injection values into entry order
+            const int64_t e = (b - part - nsb) * (TZL * TY) + threadIdx.x;
+            if (e < a.nent) {
+                const InjEntry en = a.inj.ent[e];
+                a.ev_out[e] = en.w * a.ev_src[en.pt];
+            }
+        }
         return;
     }
     int64_t L = b;
@@ -843,7 +895,10 @@ int64_t plan_t(StepArgs& a, int xchunk, int64_t resident = 0, bool single = fals
     const int64_t part = single ? (a.stencil_blocks + 7) / 8 * 8 : a.stencil_blocks;
     int64_t nsb = 0;
     if (a.smp_out && a.smp.npts > 0) nsb = (a.smp.npts + T::NT - 1) / T::NT;
-    return part + nsb;
+    // single-shot launches may gather the next step's injection values
+    int64_t ngb = 0;
+    if (single && a.ev_out && a.ev_src && a.nent > 0) ngb = (a.nent + T::NT - 1) / T::NT;
+    return part + nsb + ngb;
 }
 
 // Zero fill (the persistent graph clears its barrier words with it: a kernel

@@ -18,11 +18,16 @@ def dev():
     return torch.device("cuda:0")
 
 
-@pytest.mark.parametrize("shape,order", [((40, 52), 4), ((31, 29, 27), 8), ((36, 33), 16)])
-def test_adjoint_matches_oracle(dev, shape, order):
+@pytest.mark.parametrize("shape,order,nrec", [((40, 52), 4, 13), ((31, 29, 27), 8, 13),
+                                              ((36, 33), 16, 13), ((26, 28, 30), 8, 70),
+                                              ((50, 44), 6, 90)])
+def test_adjoint_matches_oracle(dev, shape, order, nrec):
+    """Sparse receiver sets (13 points) read the injected values directly;
+    dense ones (70 points in 3D, 90 in 2D: at least 256 entries) use the
+    values gathered into entry order a step ahead."""
     import torch
     from paper_1609_03361_amd import api
-    p = synth.random_problem(shape, order, 40, seed=order, nsrc=3, nrec=13)
+    p = synth.random_problem(shape, order, 40, seed=order, nsrc=3, nrec=nrec)
     print(f"case {p.name}", flush=True)
     geom, m, eta, q = device_inputs(p, dev)
     rng = np.random.default_rng(2)

@@ -121,7 +121,8 @@ def test_gradient_matches_oracle(dev, shape, order, nt, every):
           f"(bound {bound / ref['J']:.2e})", flush=True)
     record(f"gradient {p.name} every={every}", rel_l2=eg, fp32_oracle=floor,
            misfit_rel=ej / ref["J"])
-    assert eg < 1e-4
+    # measured 1.4e-6 .. 2.0e-6, the FP32 oracle 1.3e-6 .. 5.5e-6 on these cases
+    assert eg < 6e-6
     assert eg <= 2 * floor
     assert ej <= bound
 
@@ -178,8 +179,10 @@ def test_reduced_precision_checkpoints_on_padded_rows(dev, dtype, tol):
                           d_obs)
     e32 = rel_l2(g32.cpu().numpy(), ref["grad"])
     print(f"{dtype} checkpoints vs FP32 checkpoints: {e:.2e}; FP32 vs oracle {e32:.2e}", flush=True)
+    record(f"gradient {p.name} {dtype} checkpoints on padded rows", added=e, fp32_rel_l2=e32)
+    # measured: BF16 adds 4.2e-4, FP16 3.3e-5; the FP32 path is 4.4e-6 from the oracle
     assert e < tol
-    assert e32 < 1e-4
+    assert e32 < 1e-5
     assert float(Jr) == float(J32)      # the misfit comes from the forward run only
 
 

@@ -17,8 +17,10 @@ pytestmark = pytest.mark.gpu
 # data, so an FP32 trace error of relative size e (<= 1e-5, the wavefield
 # tolerance) reaches r, and through the adjoint the gradient, amplified by
 # |d|/|r|.  The FP32 gradient is therefore held to 1e-5 |d|/|r|; the error
-# that BF16/FP16 checkpoints add on top of the FP32 path is stated separately.
-ADDED = {"fp16": 2e-4, "bf16": 2e-3}
+# that BF16/FP16 checkpoints add on top of the FP32 path is held to about three
+# times what it measures (FP16 8.1e-6, BF16 6.8e-5: the codec rounds u^c and
+# the scaled difference to an 11- and 8-bit significand).
+ADDED = {"fp16": 2.5e-5, "bf16": 2e-4}
 
 
 @pytest.fixture(scope="module")

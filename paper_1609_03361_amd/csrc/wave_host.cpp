@@ -502,8 +502,8 @@ TileCfg cached_tile(const std::string& key, const Geo& G)
 }
 
 // opts->tile: 0 = cached or default, else an explicit id that must name an
-// existing block shape.
-int pick_tile(const wave_opts* o, const std::string& key, const Geo& G, TileCfg* out)
+// existing block shape (the two-step 2D slab only where `batch`).
+int pick_tile(const wave_opts* o, const std::string& key, const Geo& G, TileCfg* out, bool batch = false)
 {
     if (o->tile < 0) return fail(WAVE_EINVAL, "tile id %d is negative", o->tile);
     if (o->tile == 0) {
@@ -511,9 +511,14 @@ int pick_tile(const wave_opts* o, const std::string& key, const Geo& G, TileCfg*
         return WAVE_OK;
     }
     const TileCfg c = tile_from_id(o->tile);
+    if (batch && G.ndim == 2 && c.variant == kTwoStepVariant) {
+        *out = c;
+        return WAVE_OK;
+    }
     if (c.variant >= tile_variants(G.ndim, G.nzp))
-        return fail(WAVE_EINVAL, "tile variant %d does not exist (%dD has %d)", c.variant, G.ndim,
-                    tile_variants(G.ndim, G.nzp));
+        return fail(WAVE_EINVAL, "tile variant %d does not exist (%dD has %d%s)", c.variant, G.ndim,
+                    tile_variants(G.ndim, G.nzp),
+                    G.ndim == 2 ? "; the two-step variant 4 runs in wave_forward_batch only" : "");
     *out = c;
     return WAVE_OK;
 }
@@ -911,13 +916,15 @@ int run_backward(const Ctx& C, const float* q, const float* r, const CkptView& c
 // ---------------------------------------------------------------------------
 // Candidate tiles: every block shape with x-chunks of 2R, 4R, 8 .. 128
 // planes and of a half, a third and a quarter of the grid, each clamped to
-// what the shape accepts (the 2D slab holds at most 16 rows) and to the grid,
-// so that no two candidates launch the same thing.
-std::vector<TileCfg> tile_candidates(int ndim, int half, int64_t nx, int64_t nz)
+// what the shape accepts (the 2D slabs hold at most 16 rows) and to the grid,
+// so that no two candidates launch the same thing.  Batched 2D shots also
+// try the two-step slab.
+std::vector<TileCfg> tile_candidates(int ndim, int half, int64_t nx, int64_t nz, bool batch = false)
 {
     std::vector<TileCfg> out;
     const int64_t xs[] = {2 * half, 4 * half, 8, 16, 32, 64, 128, (nx + 1) / 2, (nx + 2) / 3, (nx + 3) / 4};
-    for (int v = 0; v < tile_variants(ndim, nz); ++v)
+    const int nv = tile_variants(ndim, nz) + ((batch && ndim == 2) ? 1 : 0);   // + the two-step slab
+    for (int v = 0; v < nv; ++v)
         for (int64_t x : xs) {
             if (x < 2 * half) continue;
             TileCfg c;
@@ -950,7 +957,7 @@ struct BatchShot {
     Geo G;
     HostPoints rec, src;
     HostInject inj;
-    size_t alpha = 0, beta = 0, buf0 = 0, buf1 = 0, smp_base = 0, smp_w = 0, inj_ptr = 0, inj_ent = 0;
+    size_t alpha = 0, beta = 0, buf[4] = {0, 0, 0, 0}, smp_base = 0, smp_w = 0, inj_ptr = 0, inj_ent = 0;
 };
 
 struct BatchPlan {
@@ -991,8 +998,9 @@ int batch_plan(int32_t nshots, const wave_shot* shots, BatchPlan* B, bool build_
         const int nc = 1 << S.G.ndim;
         S.alpha = c.take(N * 4);
         S.beta = c.take(N * 4);
-        S.buf0 = c.take(N * 4);
-        S.buf1 = c.take(N * 4);
+        // 2D shots keep a second wavefield pair for the two-step slab, whose
+        // passes read one pair and write the other
+        for (int k = 0; k < (S.G.ndim == 2 ? 4 : 2); ++k) S.buf[k] = c.take(N * 4);
         S.smp_base = c.take((size_t)nr * 8);
         S.smp_w = c.take((size_t)nr * nc * 4);
         S.inj_ptr = c.take(((size_t)S.G.nrows() + 1) * 4);
@@ -1050,8 +1058,8 @@ void build_descs(const BatchPlan& B, const wave_shot* shots, char* ws, TileCfg c
         D.a.smp_out = S.rec.npts ? shots[i].d : nullptr;   // marks sampling as active for planning
         const int64_t nb = plan_tiles(S.G.ndim, S.G.order, cfg, D.a);
         D.a.smp_out = nullptr;
-        D.buf[0] = reinterpret_cast<float*>(ws + S.buf0);
-        D.buf[1] = reinterpret_cast<float*>(ws + S.buf1);
+        for (int k = 0; k < 4; ++k)
+            D.buf[k] = (k < 2 || S.G.ndim == 2) ? reinterpret_cast<float*>(ws + S.buf[k]) : nullptr;
         D.q = shots[i].q;
         D.d = S.rec.npts ? shots[i].d : nullptr;
         D.nsrc = S.src.npts;
@@ -1120,8 +1128,8 @@ int batch_setup(const BatchPlan& B, const wave_shot* shots, char* ws, hipStream_
     }
     for (int i = 0; i < n; ++i) {
         const BatchShot& S = B.shots[i];
-        HIP_TRY(launch_fill(reinterpret_cast<float*>(ws + S.buf0), S.G.npad(), 0.f, st));
-        HIP_TRY(launch_fill(reinterpret_cast<float*>(ws + S.buf1), S.G.npad(), 0.f, st));
+        HIP_TRY(launch_fill(reinterpret_cast<float*>(ws + S.buf[0]), S.G.npad(), 0.f, st));
+        HIP_TRY(launch_fill(reinterpret_cast<float*>(ws + S.buf[1]), S.G.npad(), 0.f, st));
     }
     return WAVE_OK;
 }
@@ -1227,6 +1235,48 @@ int run_batch_persistent(const BatchPlan& B, char* ws, TileCfg cfg, int64_t item
     return WAVE_OK;
 }
 
+// Launches of a two-step run of nt steps (2D slab, variant kTwoStepVariant).
+// An odd nt starts with one step (u^1 into buffer 2); then passes of two
+// steps alternate between two buffer pairs, each sampling u^n and the
+// previous pass's intermediate u^{n-1}; a last launch samples u^{nt-1}.
+// Every level 0 .. nt-1 is sampled once.  *final_buf receives the buffer
+// that holds u^nt.
+struct Launch2 {
+    int32_t n, bufs, flags;
+};
+
+std::vector<Launch2> two_step_schedule(int nt, int* final_buf)
+{
+    auto pack = [](int c, int o, int o1, int o2) { return c | (o << 2) | (o1 << 4) | (o2 << 6); };
+    std::vector<Launch2> L;
+    const int s0 = nt & 1;
+    int pair[2][2] = {{0, 1}, {2, 3}};           // {u^n, u^{n-1}} of the passes' input pairs
+    if (s0) {
+        L.push_back({0, pack(0, 1, 2, 3), 1 | 2 | 8});
+        pair[0][0] = 2; pair[0][1] = 0;
+        pair[1][0] = 1; pair[1][1] = 3;
+    }
+    const int P = (nt - s0) / 2;
+    for (int p = 0; p < P; ++p) {
+        const int* in = pair[p & 1];
+        const int* out = pair[(p + 1) & 1];
+        L.push_back({s0 + 2 * p, pack(in[0], in[1], out[1], out[0]), 1 | 2 | (p > 0 ? 4 : 0)});
+    }
+    if (P > 0) L.push_back({nt, pack(pair[P & 1][0], pair[P & 1][1], 0, 0), 4});
+    *final_buf = pair[P & 1][0];
+    return L;
+}
+
+hipError_t launch_schedule_entry(const Geo& G, TileCfg cfg, const ShotDesc* d_desc, const int64_t* d_begin,
+                                 int nshots, int64_t blocks, int i, const std::vector<Launch2>& sched,
+                                 hipStream_t st)
+{
+    if (cfg.variant == kTwoStepVariant && G.ndim == 2)
+        return launch_batch2(G.order, d_desc, d_begin, nshots, blocks, sched[i].n, sched[i].bufs,
+                             sched[i].flags, st);
+    return launch_batch(G.ndim, G.order, G.nzp, cfg, d_desc, d_begin, nshots, blocks, i, st);
+}
+
 int run_batch_loop(const BatchPlan& B, char* ws, TileCfg cfg, int64_t blocks, hipStream_t st,
                    bool use_graph)
 {
@@ -1235,10 +1285,14 @@ int run_batch_loop(const BatchPlan& B, char* ws, TileCfg cfg, int64_t blocks, hi
     const ShotDesc* d_desc = reinterpret_cast<const ShotDesc*>(ws + B.desc);
     const int64_t* d_begin = reinterpret_cast<const int64_t*>(ws + B.begin);
     TS().batch_mode = use_graph ? 0 : 1;
+    const bool two = cfg.variant == kTwoStepVariant && G.ndim == 2;
+    int final_buf = 0;
+    const std::vector<Launch2> sched = two ? two_step_schedule(G.nt, &final_buf) : std::vector<Launch2>();
+    const int nl = two ? (int)sched.size() : G.nt;
     if (!use_graph) {
-        for (int n = 0; n < G.nt; ++n) {
+        for (int i = 0; i < nl; ++i) {
             ++TS().prof.launches;
-            HIP_TRY(launch_batch(G.ndim, G.order, G.nzp, cfg, d_desc, d_begin, nshots, blocks, n, st));
+            HIP_TRY(launch_schedule_entry(G, cfg, d_desc, d_begin, nshots, blocks, i, sched, st));
         }
         return WAVE_OK;
     }
@@ -1247,9 +1301,9 @@ int run_batch_loop(const BatchPlan& B, char* ws, TileCfg cfg, int64_t blocks, hi
         if (!TS().graph.capture) HIP_TRY(hipStreamCreateWithFlags(&TS().graph.capture, hipStreamNonBlocking));
         HIP_TRY(hipStreamBeginCapture(TS().graph.capture, hipStreamCaptureModeThreadLocal));
         hipError_t err = hipSuccess;
-        for (int n = 0; n < G.nt && err == hipSuccess; ++n)
-            err = launch_batch(G.ndim, G.order, G.nzp, cfg, d_desc, d_begin, nshots, blocks, n,
-                               TS().graph.capture);
+        for (int i = 0; i < nl && err == hipSuccess; ++i)
+            err = launch_schedule_entry(G, cfg, d_desc, d_begin, nshots, blocks, i, sched,
+                                        TS().graph.capture);
         hipGraph_t graph = nullptr;
         const hipError_t e2 = hipStreamEndCapture(TS().graph.capture, &graph);
         if (err != hipSuccess || e2 != hipSuccess) {
@@ -1260,7 +1314,7 @@ int run_batch_loop(const BatchPlan& B, char* ws, TileCfg cfg, int64_t blocks, hi
         const int rc = instantiate_cached(graph, key);
         if (rc) return rc;
     }
-    TS().prof.launches += G.nt;
+    TS().prof.launches += nl;
     HIP_TRY(hipGraphLaunch(TS().graph.exec, st));
     return WAVE_OK;
 }
@@ -1583,25 +1637,30 @@ int wave_forward_batch(int32_t nshots, const wave_shot* shots, const wave_opts* 
         hipStream_t st = static_cast<hipStream_t>(stream);
         if ((rc = batch_setup(B, shots, ws, st))) return rc;
         TileCfg cfg;
-        if ((rc = pick_tile(opts, batch_key(B), B.shots[0].G, &cfg))) return rc;
+        const Geo& G0 = B.shots[0].G;
+        if ((rc = pick_tile(opts, batch_key(B), G0, &cfg, true))) return rc;
+        const bool persistent = (opts->flags & WAVE_FLAG_PERSISTENT) != 0;
+        // the persistent kernel takes single steps: the two-step slab maps
+        // to the one-step slab there
+        if (persistent && G0.ndim == 2 && cfg.variant == kTwoStepVariant) cfg = TileCfg{3, kSlabRows};
         std::vector<ShotDesc> desc;
         std::vector<int64_t> begin;
         int64_t blocks = 0;
         build_descs(B, shots, ws, cfg, &desc, &begin, &blocks);
         if ((rc = upload_descs(desc, begin, ws, B, st))) return rc;
         if (prof_begin(st)) return fail(WAVE_EHIP, "profiling event failed");
-        if (opts->flags & WAVE_FLAG_PERSISTENT)
+        if (persistent)
             rc = run_batch_persistent(B, ws, cfg, blocks, st, !(opts->flags & WAVE_FLAG_NO_GRAPH));
         else
             rc = run_batch_loop(B, ws, cfg, blocks, st, !(opts->flags & WAVE_FLAG_NO_GRAPH));
         if (rc) return rc;
         if (prof_end(st)) return fail(WAVE_EHIP, "profiling event failed");
-        const int last = B.shots[0].G.nt & 1;
+        int last = G0.nt & 1;
+        if (G0.ndim == 2 && cfg.variant == kTwoStepVariant) (void)two_step_schedule(G0.nt, &last);
         for (int i = 0; i < nshots; ++i)
             if (shots[i].u_final) {
                 const BatchShot& S = B.shots[i];
-                HIP_TRY(copy_out(shots[i].u_final,
-                                 reinterpret_cast<const float*>(ws + (last ? S.buf1 : S.buf0)), S.G, st));
+                HIP_TRY(copy_out(shots[i].u_final, reinterpret_cast<const float*>(ws + S.buf[last]), S.G, st));
             }
         return WAVE_OK;
     } catch (const std::exception& e) {
@@ -1695,26 +1754,38 @@ int wave_tune_batch(int32_t nshots, const wave_shot* shots, const wave_opts* opt
         TileCfg best_cfg;
         const ShotDesc* d_desc = reinterpret_cast<const ShotDesc*>(ws + B.desc);
         const int64_t* d_begin = reinterpret_cast<const int64_t*>(ws + B.begin);
-        for (const TileCfg& cfg : tile_candidates(G.ndim, G.half, maxnx, G.nzp)) {
+        const bool verbose = std::getenv("WAVE_TUNE_VERBOSE") != nullptr;
+        for (const TileCfg& cfg : tile_candidates(G.ndim, G.half, maxnx, G.nzp, true)) {
             std::vector<ShotDesc> desc;
             std::vector<int64_t> begin;
             int64_t blocks = 0;
             build_descs(B, shots, ws, cfg, &desc, &begin, &blocks);
             for (ShotDesc& D : desc) { D.nsrc = 0; D.nrec = 0; D.d = nullptr; }   // no outputs touched
             if ((rc = upload_descs(desc, begin, ws, B, st))) return rc;
-            for (int w = 0; w < 2; ++w)
-                HIP_TRY(launch_batch(G.ndim, G.order, G.nzp, cfg, d_desc, d_begin, nshots, blocks, w, st));
+            // a two-step launch advances two levels: pass n reads buffers 0/1
+            // and writes 3/2, timed per level
+            const bool two = G.ndim == 2 && cfg.variant == kTwoStepVariant;
+            auto once = [&](int i) {
+                return two ? launch_batch2(G.order, d_desc, d_begin, nshots, blocks, 2 * i,
+                                             0 | (1 << 2) | (3 << 4) | (2 << 6), 1, st)
+                           : launch_batch(G.ndim, G.order, G.nzp, cfg, d_desc, d_begin, nshots, blocks, i, st);
+            };
+            const int launches = two ? (steps + 1) / 2 : steps;
+            const int levels = two ? 2 * launches : steps;
+            for (int w = 0; w < 2; ++w) HIP_TRY(once(w));
             double t = 1e300;
             for (int rep = 0; rep < 3; ++rep) {
                 HIP_TRY(hipEventRecord(ev.a, st));
-                for (int i = 0; i < steps; ++i)
-                    HIP_TRY(launch_batch(G.ndim, G.order, G.nzp, cfg, d_desc, d_begin, nshots, blocks, i, st));
+                for (int i = 0; i < launches; ++i) HIP_TRY(once(i));
                 HIP_TRY(hipEventRecord(ev.b, st));
                 HIP_TRY(hipEventSynchronize(ev.b));
                 float ms = 0.f;
                 HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
-                t = std::min(t, 1e3 * ms / steps);
+                t = std::min(t, 1e3 * ms / levels);
             }
+            if (verbose)
+                std::fprintf(stderr, "wave_tune_batch: variant %d x-chunk %d: %.2f us per step\n",
+                             cfg.variant, cfg.xchunk, t);
             if (t < best) { best = t; best_cfg = cfg; }
         }
         *tile = tile_id(best_cfg);

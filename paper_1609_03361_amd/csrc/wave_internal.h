@@ -83,7 +83,8 @@ struct StepArgs {
 // pointers that the step index selects from.
 struct ShotDesc {
     StepArgs a;          // cur/other/out/inj_val/smp_out are set per step
-    float* buf[2];       // wavefield pair: even steps read buf[0], odd steps buf[1]
+    float* buf[4];       // wavefield pair: even steps read buf[0], odd steps buf[1];
+                         // the two-step slab (2D) rotates through all four
     const float* q;      // [nt][nsrc]
     float* d;            // [nt][nrec] or nullptr
     int32_t nsrc, nrec;
@@ -109,6 +110,11 @@ hipError_t noalloc_scratch(void** ptr);
 // Rows of u^n a 2D slab block computes at most (its x-chunk); the LDS slab
 // holds them with R halo rows on either side.
 constexpr int kSlabRows = 16;
+// The two-step slab (2D tile variant kTwoStepVariant, batched shots only):
+// owned rows per x-chunk at most, and threads per block (eight waves).
+constexpr int kSlab2Rows = 16;
+constexpr int kSlab2Threads = 512;
+constexpr int kTwoStepVariant = 4;
 
 // Block shapes of the step kernel: z-points per lane, lanes along z and rows
 // along y (2D: rows along x, computed by the slab body when > 1).
@@ -142,6 +148,8 @@ struct OrderOps {
     static hipError_t batch(int ndim, int64_t nz_any, TileCfg cfg, const ShotDesc* shots,
                             const int64_t* begin, int32_t nshots, int64_t blocks, int32_t n,
                             hipStream_t s);
+    static hipError_t batch2(const ShotDesc* shots, const int64_t* begin, int32_t nshots,
+                             int64_t blocks, int32_t n, int32_t bufs, int32_t flags, hipStream_t s);
     static hipError_t persistent(int ndim, int64_t nz_any, TileCfg cfg, const ShotDesc* shots,
                                  const int64_t* begin, int32_t nshots, int64_t items, int32_t nt,
                                  unsigned int* sync, int32_t spin_limit, int* grid_used,
@@ -153,8 +161,9 @@ struct OrderOps {
                                        hipGraph_t* graph);
 };
 
-// Number of block-shape variants for a grid (2D: 4, 3D: 6; the row length
-// handed to the kernels is always a multiple of 4).
+// Number of single-step block-shape variants for a grid (2D: 4, 3D: 11; the
+// row length handed to the kernels is always a multiple of 4).  Batched 2D
+// shots also accept kTwoStepVariant.
 int tile_variants(int ndim, int64_t nz);
 // Longest x-chunk a block shape accepts (the 2D slab holds at most 16 rows;
 // the streaming shapes have no limit below the grid).
@@ -177,6 +186,10 @@ hipError_t launch_step(int ndim, int order, const StepArgs& a, hipStream_t s, Ti
 hipError_t launch_batch(int ndim, int order, int64_t nz_any, TileCfg cfg, const ShotDesc* shots,
                         const int64_t* begin, int32_t nshots, int64_t blocks, int32_t n,
                         hipStream_t s);
+// Two steps of every shot in one launch (2D, tile variant kTwoStepVariant,
+// shots planned with it): n, bufs and flags as k_step_batch2 documents them.
+hipError_t launch_batch2(int order, const ShotDesc* shots, const int64_t* begin, int32_t nshots,
+                         int64_t blocks, int32_t n, int32_t bufs, int32_t flags, hipStream_t s);
 // All nt steps of all shots in one cooperative (co-resident) launch with a
 // device-wide barrier per step.  `sync` = {arrival counter, error word}, both
 // zero at launch; the error word is set if a barrier wait exceeded

@@ -377,7 +377,9 @@ int tile_variants(int ndim, int64_t)
 
 int max_xchunk(int ndim, int variant)
 {
-    return (ndim == 2 && variant == 3) ? kSlabRows : (1 << 30);
+    if (ndim == 2 && variant == 3) return kSlabRows;
+    if (ndim == 2 && variant == kTwoStepVariant) return kSlab2Rows;
+    return 1 << 30;
 }
 
 int default_variant(int ndim, int order, int64_t ny, int64_t nz)
@@ -435,6 +437,14 @@ hipError_t launch_batch(int ndim, int order, int64_t nz_any, TileCfg cfg, const 
                         hipStream_t s)
 {
 #define WAVE_CASE(O) case O: return OrderOps<O>::batch(ndim, nz_any, cfg, shots, begin, nshots, blocks, n, s);
+    switch (order) { WAVE_ORDERS(WAVE_CASE) default: return hipErrorInvalidValue; }
+#undef WAVE_CASE
+}
+
+hipError_t launch_batch2(int order, const ShotDesc* shots, const int64_t* begin, int32_t nshots,
+                         int64_t blocks, int32_t n, int32_t bufs, int32_t flags, hipStream_t s)
+{
+#define WAVE_CASE(O) case O: return OrderOps<O>::batch2(shots, begin, nshots, blocks, n, bufs, flags, s);
     switch (order) { WAVE_ORDERS(WAVE_CASE) default: return hipErrorInvalidValue; }
 #undef WAVE_CASE
 }

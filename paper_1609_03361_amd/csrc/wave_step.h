@@ -189,17 +189,18 @@ __device__ __forceinline__ void z_terms(const float* Lc, const Vec<VZ>& c, const
 // time: loading several ahead held enough registers to cost the 512^3
 // order-16 step a wave per SIMD.
 template <int VZ>
-__device__ __forceinline__ void inject_entries(const StepArgs& a, int32_t e0, int32_t e1, int64_t z,
-                                               const Vec<VZ>& al, Vec<VZ>& o)
+__device__ __forceinline__ void inject_core(const InjEntry* __restrict__ ent, const float* __restrict__ ev,
+                                            const float* __restrict__ val, int32_t e0, int32_t e1,
+                                            int64_t z, const Vec<VZ>& al, Vec<VZ>& o)
 {
     float acc[VZ];
     bool hit[VZ];
 #pragma unroll
     for (int v = 0; v < VZ; ++v) { acc[v] = 0.f; hit[v] = false; }
     for (int32_t e = e0; e < e1; ++e) {
-        const InjEntry en = a.inj.ent[e];
+        const InjEntry en = ent[e];
         // w * val rounded, then added: the gathered values hold the same products
-        const float wv = a.inj_ev ? a.inj_ev[e] : en.w * a.inj_val[en.pt];
+        const float wv = ev ? ev[e] : en.w * val[en.pt];
         const int64_t dz = (int64_t)en.z - z;
 #pragma unroll
         for (int v = 0; v < VZ; ++v)
@@ -213,6 +214,28 @@ __device__ __forceinline__ void inject_entries(const StepArgs& a, int32_t e0, in
         if (hit[v]) o[v] = fmaf(al[v], acc[v], o[v]);
 }
 
+template <int VZ>
+__device__ __forceinline__ void inject_entries(const StepArgs& a, int32_t e0, int32_t e1, int64_t z,
+                                               const Vec<VZ>& al, Vec<VZ>& o)
+{
+    inject_core<VZ>(a.inj.ent, a.inj_ev, a.inj_val, e0, e1, z, al, o);
+}
+
+// The leapfrog update of the VZ points of one lane:
+// out = fma(alpha, lap, fma(beta, u - other, u)).
+template <int VZ>
+__device__ __forceinline__ Vec<VZ> update_core(const Vec<VZ>& c, const float* lap, const Vec<VZ>& uo,
+                                               const Vec<VZ>& al, const Vec<VZ>& be)
+{
+    Vec<VZ> o;
+#pragma unroll
+    for (int v = 0; v < VZ; ++v) {
+        const float w = fmaf(be[v], c[v] - uo[v], c[v]);
+        o[v] = fmaf(al[v], lap[v], w);
+    }
+    return o;
+}
+
 // The leapfrog update of the VZ points of one lane, then the owner-gather
 // injection of the entries [e0, e1) of the lane's row (e1 == e0 when the row
 // holds no injected node; the range was fetched with the other per-row
@@ -224,12 +247,7 @@ __device__ __forceinline__ Vec<VZ> update_inject(const StepArgs& a, const Vec<VZ
                                                  const Vec<VZ>& uo, const Vec<VZ>& al, const Vec<VZ>& be,
                                                  int32_t e0, int32_t e1, int64_t z)
 {
-    Vec<VZ> o;
-#pragma unroll
-    for (int v = 0; v < VZ; ++v) {
-        const float w = fmaf(be[v], c[v] - uo[v], c[v]);
-        o[v] = fmaf(al[v], lap[v], w);
-    }
+    Vec<VZ> o = update_core<VZ>(c, lap, uo, al, be);
     if (e1 > e0) inject_entries<VZ>(a, e0, e1, z, al, o);
     return o;
 }
@@ -802,6 +820,215 @@ __global__ __launch_bounds__(TZL* TY) void k_batch_persistent(const ShotDesc* __
     }
 }
 
+// Two time steps per pass (temporal blocking, 2D): levels n+1 and n+2 from
+// u^n and u^{n-1} in one read of the fields.  A block of eight waves owns
+// TZO = 256 - 2 RZ z-points over an x-chunk of at most kSlab2Rows rows; its
+// lanes cover the owned z plus RZ on either side.
+//   1. rows xa-2R .. xb+2R-1 of u^n (z halo RZ beyond the lanes) go to LDS;
+//      u^{n-1}, alpha and beta of rows xa-R .. xb+R-1 to registers;
+//   2. step 1 computes u^{n+1} on rows xa-R .. xb+R-1 at every lane (zero
+//      outside the grid), with the level-n injection; the owned part goes to
+//      `out1`;
+//   3. after a barrier the block overwrites u^n in LDS with u^{n+1} (u^n of
+//      its own points stays in registers);
+//   4. step 2 computes u^{n+2} on the owned rows and lanes, with the level
+//      n+1 injection, into `a.out`.
+// Each point's arithmetic is that of the single step (same operations in the
+// same order), and a point outside the block's own part is computed from the
+// same inputs as by the block that owns it, so two steps here are bitwise two
+// single steps.  The inputs are not written during the pass, which is why the
+// outputs go to a second pair of buffers: 20 + 4 (4R/XR) + 12 (2R/XR) + 4 B
+// read and written per two updates instead of 2 x (20 + 4 (2R/XR)).
+template <int R, int VZ, int TZL, int TW>
+__device__ __forceinline__ void slab2_body(const StepArgs& a, int64_t L, const float* __restrict__ val0,
+                                           const float* __restrict__ val1, float* __restrict__ out1,
+                                           bool two)
+{
+    constexpr int NT = TZL * TW;
+    constexpr int RZ = (R + VZ - 1) / VZ * VZ;
+    constexpr int TZE = TZL * VZ;                  // z the lanes cover
+    constexpr int TZO = TZE - 2 * RZ;              // z a block owns
+    constexpr int PITCH = TZE + 2 * RZ;
+    constexpr int XR = kSlab2Rows, NE = XR + 2 * R, ROWS = XR + 4 * R, NV = PITCH / VZ;
+    constexpr int S = (NE + TW - 1) / TW;          // step-1 rows per wave
+    static_assert(NE <= 64, "the injection rows of a chunk are one wave-wide ballot");
+    static_assert(TZL % 64 == 0, "one wave per row group keeps the row test uniform");
+    static_assert(TZO > 0 && TZO % VZ == 0, "owned z must be whole vectors");
+    __shared__ __attribute__((aligned(16))) float lds[ROWS * PITCH];
+
+    const int64_t nx = a.nx, nz = a.nz;
+    const int tid = threadIdx.x;
+    const int tzi = (int)(L % a.ntz);
+    const int64_t chunk = L / a.ntz;
+    const int tz = tid % TZL, tw = tid / TZL;
+    const int64_t z0 = (int64_t)tzi * TZO;         // first owned z
+    const int64_t z = z0 - RZ + (int64_t)tz * VZ;  // the lane's first point
+    // nz and z are multiples of VZ: a lane's points are all inside or all out
+    const bool zin = z >= 0 && z < nz;
+    const bool zown = zin && tz >= RZ / VZ && tz < TZL - RZ / VZ;
+    const int64_t xa = chunk * a.xchunk;
+    const int64_t xb = xa + a.xchunk < nx ? xa + a.xchunk : nx;
+    const int count = (int)(xb - xa);              // at most XR (planner)
+    const int ne = count + 2 * R;
+
+    for (int i = tid; i < (count + 4 * R) * NV; i += NT) {
+        const int r = i / NV, k = i - r * NV;
+        const int64_t xx = xa - 2 * R + r, zz = z0 - 2 * RZ + (int64_t)k * VZ;
+        Vec<VZ> v = vzero<VZ>();
+        if (xx >= 0 && xx < nx && zz >= 0 && zz < nz) v = vload<VZ>(a.cur + xx * nz + zz);
+        vstore<VZ>(lds + r * PITCH + k * VZ, v);
+    }
+    // rows of the widened chunk that hold injected nodes (one ballot)
+    const int32_t* rp = a.inj.row_ptr;
+    const bool inj_any = val0 && xb + R > a.inj_x0 && xa - R <= a.inj_x1;
+    uint64_t inj_rows = 0;
+    if (inj_any) {
+        const int lane = tid & 63;
+        const int64_t x = xa - R + lane;
+        inj_rows = __ballot(lane < ne && x >= 0 && x < nx && rp[x + 1] != rp[x]);
+    }
+    Vec<VZ> uo[S], al[S], be[S];
+    int32_t e0[S], e1[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const int r = tw + k * TW;
+        const int64_t x = xa - R + r;
+        const bool in = r < ne && x >= 0 && x < nx && zin;
+        e0[k] = e1[k] = 0;
+        if (in && ((inj_rows >> r) & 1u)) {
+            e0[k] = rp[x];
+            e1[k] = rp[x + 1];
+        }
+        uo[k] = al[k] = be[k] = vzero<VZ>();
+        if (in) {
+            const int64_t off = x * nz + z;
+            if (!a.no_prev) {
+                uo[k] = vload<VZ>(a.other + off);
+                be[k] = vload<VZ>(a.beta + off);
+            }
+            al[k] = vload<VZ>(a.alpha + off);
+        }
+    }
+    __syncthreads();
+
+    // step 1: u^{n+1} on the widened rows
+    Vec<VZ> o1[S], cc[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const int r = tw + k * TW;
+        o1[k] = cc[k] = vzero<VZ>();
+        if (r >= ne) continue;                     // uniform within a wave
+        const int64_t x = xa - R + r;
+        const float* Lc = lds + (r + R) * PITCH + RZ + tz * VZ;
+        const Vec<VZ> c = vload<VZ>(Lc);
+        float lap[VZ], m2c[VZ];
+#pragma unroll
+        for (int v = 0; v < VZ; ++v) {
+            lap[v] = 0.f;
+            m2c[v] = -2.f * c[v];
+        }
+#pragma unroll
+        for (int j = 1; j <= R; ++j) {
+            const Vec<VZ> p = vload<VZ>(Lc + j * PITCH);
+            const Vec<VZ> m = vload<VZ>(Lc - j * PITCH);
+#pragma unroll
+            for (int v = 0; v < VZ; ++v) lap[v] = fmaf(a.cx[j], (p[v] + m[v]) + m2c[v], lap[v]);
+        }
+        z_terms<R, VZ, RZ>(Lc, c, m2c, a.cz, lap);
+        Vec<VZ> o = update_core<VZ>(c, lap, uo[k], al[k], be[k]);
+        if (e1[k] > e0[k]) inject_core<VZ>(a.inj.ent, nullptr, val0, e0[k], e1[k], z, al[k], o);
+        if (x >= 0 && x < nx && zin) {
+            o1[k] = o;
+            cc[k] = c;
+            if (zown && r >= R && r < R + count) vstore<VZ>(out1 + x * nz + z, o);
+        }
+    }
+    if (!two) return;                              // one step only (uniform)
+    __syncthreads();                               // every wave is done with u^n in LDS
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const int r = tw + k * TW;
+        if (r < ne) vstore<VZ>(lds + (r + R) * PITCH + RZ + tz * VZ, o1[k]);
+    }
+    __syncthreads();
+
+    // step 2: u^{n+2} on the owned rows
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const int r = tw + k * TW;
+        if (r >= ne) break;                        // uniform within a wave
+        if (r < R || r >= R + count) continue;
+        const int64_t x = xa - R + r;
+        const float* Lc = lds + (r + R) * PITCH + RZ + tz * VZ;
+        const Vec<VZ> c = vload<VZ>(Lc);
+        float lap[VZ], m2c[VZ];
+#pragma unroll
+        for (int v = 0; v < VZ; ++v) {
+            lap[v] = 0.f;
+            m2c[v] = -2.f * c[v];
+        }
+#pragma unroll
+        for (int j = 1; j <= R; ++j) {
+            const Vec<VZ> p = vload<VZ>(Lc + j * PITCH);
+            const Vec<VZ> m = vload<VZ>(Lc - j * PITCH);
+#pragma unroll
+            for (int v = 0; v < VZ; ++v) lap[v] = fmaf(a.cx[j], (p[v] + m[v]) + m2c[v], lap[v]);
+        }
+        z_terms<R, VZ, RZ>(Lc, c, m2c, a.cz, lap);
+        Vec<VZ> o = update_core<VZ>(c, lap, cc[k], al[k], be[k]);
+        if (e1[k] > e0[k]) inject_core<VZ>(a.inj.ent, nullptr, val1, e0[k], e1[k], z, al[k], o);
+        if (zown) vstore<VZ>(a.out + x * nz + z, o);
+    }
+}
+
+// Two steps of every shot in one launch (2D, the slab2 body): levels n+1 and
+// n+2 from buffers buf[bufs & 3] (u^n) and buf[(bufs >> 2) & 3] (u^{n-1})
+// into buf[(bufs >> 4) & 3] (u^{n+1}) and buf[(bufs >> 6) & 3] (u^{n+2}),
+// with the injection rows n and n+1.  Blocks past a shot's tiles sample
+// u^n into row n of d (flags & 2) and u^{n-1} into row n-1 (flags & 4);
+// flags & 1 runs the tiles (a launch with flags 4 only samples, after the
+// last pass); with flags & 8 the tiles take one step only (u^{n+1} into
+// buf[(bufs >> 4) & 3]), which starts a run with an odd number of steps.
+template <int R>
+__global__ __launch_bounds__(kSlab2Threads) void k_step_batch2(const ShotDesc* __restrict__ shots,
+                                                               const int64_t* __restrict__ begin,
+                                                               int32_t nshots, int32_t n, int32_t bufs,
+                                                               int32_t flags)
+{
+    constexpr int NT = kSlab2Threads;
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = nshots - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (begin[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const ShotDesc& D = shots[lo];
+    StepArgs a = D.a;
+    const float* u0 = D.buf[bufs & 3];
+    const float* um = D.buf[(bufs >> 2) & 3];
+    const int64_t lb = b - begin[lo];
+    if (lb >= a.stencil_blocks) {
+        const int64_t nsb = (a.smp.npts + NT - 1) / NT;
+        const int64_t sb = lb - a.stencil_blocks;
+        const bool second = sb >= nsb;
+        const int64_t p = (second ? sb - nsb : sb) * NT + threadIdx.x;
+        if (p < a.smp.npts && D.d) {
+            if (!second && (flags & 2)) D.d[(int64_t)n * D.nrec + p] = sample_point<2>(a.smp, u0, p, a.nz, a.nz);
+            if (second && (flags & 4) && n >= 1)
+                D.d[(int64_t)(n - 1) * D.nrec + p] = sample_point<2>(a.smp, um, p, a.nz, a.nz);
+        }
+        return;
+    }
+    if (!(flags & 1)) return;
+    a.cur = u0;
+    a.other = um;
+    a.out = D.buf[(bufs >> 6) & 3];
+    const float* v0 = D.nsrc ? D.q + (int64_t)n * D.nsrc : nullptr;
+    const float* v1 = D.nsrc ? D.q + (int64_t)(n + 1) * D.nsrc : nullptr;
+    slab2_body<R, 4, 64, kSlab2Threads / 64>(a, lb, v0, v1, D.buf[(bufs >> 4) & 3], !(flags & 8));
+}
+
 template <int DIM_, int R_, int VZ_, int TZL_, int TY_>
 struct Cfg {
     static constexpr int DIM = DIM_, R = R_, VZ = VZ_, TZL = TZL_, TY = TY_;
@@ -901,6 +1128,27 @@ int64_t plan_t(StepArgs& a, int xchunk, int64_t resident = 0, bool single = fals
     return part + nsb + ngb;
 }
 
+// Plan of the two-step slab (2D): tiles of 256 - 2 RZ owned z, x-chunks of
+// at most kSlab2Rows rows; two sampler groups per shot (u^n and u^{n-1}).
+template <int R>
+int64_t plan_t2(StepArgs& a, int xchunk)
+{
+    constexpr int RZ = (R + 3) / 4 * 4;
+    constexpr int TZO = 256 - 2 * RZ;
+    if (a.nz % 4 != 0) return -1;
+    a.ntz = (int32_t)((a.nz + TZO - 1) / TZO);
+    a.nty = 1;
+    if (xchunk <= 0 || xchunk > kSlab2Rows) xchunk = kSlab2Rows;
+    if (xchunk > a.nx) xchunk = (int)a.nx;
+    a.xchunk = xchunk;
+    const int64_t nchunk = (a.nx + xchunk - 1) / xchunk;
+    a.stencil_blocks = (int64_t)a.ntz * nchunk;
+    a.remap = 0;
+    int64_t nsb = 0;
+    if (a.smp_out && a.smp.npts > 0) nsb = 2 * ((a.smp.npts + kSlab2Threads - 1) / kSlab2Threads);
+    return a.stencil_blocks + nsb;
+}
+
 // Zero fill (the persistent graph clears its barrier words with it: a kernel
 // node, not a memset node).
 __global__ __launch_bounds__(kBlock) void k_zero(float* __restrict__ p, int64_t n)
@@ -962,6 +1210,7 @@ int64_t step_resident()
 template <int O>
 int64_t OrderOps<O>::plan(int ndim, TileCfg cfg, StepArgs& a, bool device)
 {
+    if (ndim == 2 && cfg.variant == kTwoStepVariant) return plan_t2<O / 2>(a, cfg.xchunk);
     int64_t blocks = -1;
     auto f = [&](auto C) {
         using CC = decltype(C);
@@ -1006,6 +1255,15 @@ hipError_t OrderOps<O>::batch(int ndim, int64_t nz_any, TileCfg cfg, const ShotD
         return hipGetLastError();
     };
     return ndim == 2 ? with_shape<2, O / 2>(cfg.variant, nz_any, f) : with_shape<3, O / 2>(cfg.variant, nz_any, f);
+}
+
+template <int O>
+hipError_t OrderOps<O>::batch2(const ShotDesc* shots, const int64_t* begin, int32_t nshots,
+                               int64_t blocks, int32_t n, int32_t bufs, int32_t flags, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_step_batch2<O / 2>, dim3((unsigned)blocks), dim3(kSlab2Threads), 0, s, shots,
+                       begin, nshots, n, bufs, flags);
+    return hipGetLastError();
 }
 
 template <int O>

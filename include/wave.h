@@ -90,10 +90,11 @@ typedef struct {
                                  planned).  Variants (block shapes, z x rows of the (y, z)
                                  plane): 2D 0 = 256 z (4 per lane), 1 = 128 z (1 per lane),
                                  2 = 128 z (2 per lane), 3 = 256 z with x-chunks of at most
-                                 16 rows held in LDS, 4 (wave_forward_batch only) = two
-                                 time steps per pass over x-chunks of at most 16 rows
-                                 (temporal blocking, 256 - 2 ceil4(R) owned z per block,
-                                 see wave_forward_batch); 3D 0 = 64 x 16, 1 = 64 x 8,
+                                 16 rows held in LDS, 4 (wave_forward_batch only, its
+                                 default in 2D) = two time steps per pass over columns of
+                                 x-chunk rows, 64 when planned (temporal blocking,
+                                 256 - 2 ceil4(R) owned z per block, see
+                                 wave_forward_batch); 3D 0 = 64 x 16, 1 = 64 x 8,
                                  2 = 32 x 32, 3 = 100 x 10, 4 = 200 x 5 (4 z-points per
                                  lane), 5 = 64 x 8 (2 per lane), 6 = 64 x 32 (4 per lane),
                                  7 = 64 x 16, 8 = 64 x 32 (2 per lane), 9 = 128 x 16
@@ -244,14 +245,15 @@ typedef struct {
 int wave_batch_workspace_size(int32_t nshots, const wave_shot* shots, const wave_opts* opts,
                               size_t* bytes);
 /* 2D tile variant 4 (temporal blocking, Section "Loop Blocking" applied to
- * time as well): each launch advances every shot by two steps, computing
- * level n+1 on the block's rows widened by R on either side (and its z
- * widened by ceil4(R)) and level n+2 on its own points, from one read of u^n,
- * u^{n-1}, alpha and beta.  The passes read one wavefield pair and write
- * the other, so the workspace of a 2D batch holds four wavefields per shot;
- * an odd nt starts with one step, and the receivers of level n-1 are sampled
- * by the pass that reads it.  Results are bitwise those of the one-step
- * variants.  With WAVE_FLAG_PERSISTENT the variant maps to 3 (the
+ * time as well; the default for 2D batches): each launch advances every
+ * shot by two steps.  A block walks a column of x-chunk rows eight rows at a
+ * time, computing level n+1 on its rows and R rows beyond them (and on its z
+ * widened by ceil4(R)) and level n+2 on its own points, from one read of
+ * u^n, u^{n-1}, alpha and beta.  The passes read one wavefield pair and
+ * write the other, so the workspace of a 2D batch holds four wavefields per
+ * shot; an odd nt starts with one step, and the receivers of level n-1 are
+ * sampled by the pass that reads it.  Results are bitwise those of the
+ * one-step variants.  With WAVE_FLAG_PERSISTENT the variant maps to 3 (the
  * persistent kernel takes one step at a time). */
 /* With opts->flags & WAVE_FLAG_PERSISTENT the whole time loop of all shots is
  * one cooperative launch (all its blocks are resident at once; the grid is

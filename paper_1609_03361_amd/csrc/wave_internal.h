@@ -110,9 +110,10 @@ hipError_t noalloc_scratch(void** ptr);
 // Rows of u^n a 2D slab block computes at most (its x-chunk); the LDS slab
 // holds them with R halo rows on either side.
 constexpr int kSlabRows = 16;
-// The two-step slab (2D tile variant kTwoStepVariant, batched shots only):
-// owned rows per x-chunk at most, and threads per block (eight waves).
-constexpr int kSlab2Rows = 16;
+// The two-step body (2D tile variant kTwoStepVariant, batched shots only):
+// the default column length and the threads per block (eight waves, one per
+// row of a round of its walk along the column).
+constexpr int kSlab2Column = 64;
 constexpr int kSlab2Threads = 512;
 constexpr int kTwoStepVariant = 4;
 

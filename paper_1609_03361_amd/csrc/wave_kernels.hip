@@ -378,7 +378,6 @@ int tile_variants(int ndim, int64_t)
 int max_xchunk(int ndim, int variant)
 {
     if (ndim == 2 && variant == 3) return kSlabRows;
-    if (ndim == 2 && variant == kTwoStepVariant) return kSlab2Rows;
     return 1 << 30;
 }
 

@@ -31,20 +31,59 @@
 #ifndef WAVE_LEAD_MAX_R
 #define WAVE_LEAD_MAX_R 6
 #endif
+#ifndef WAVE_SLAB2_WPE
+#define WAVE_SLAB2_WPE 4
+#endif
+#ifndef WAVE_BATCH2_REMAP
+#define WAVE_BATCH2_REMAP 0
+#endif
 
 namespace wave {
 
 namespace {
 
 
+// Global memory is addressed through pointers in the global address space.
+// A generic pointer that the compiler cannot trace to a kernel argument
+// (the batch kernels read theirs from the shot descriptors) would otherwise
+// compile to flat loads, which count against the LDS counter as well: every
+// wait for an LDS result, and every LDS barrier, would then also wait for all
+// outstanding global loads.
+#define WAVE_GLOBAL __attribute__((address_space(1)))
+
+template <class T>
+__device__ __forceinline__ const WAVE_GLOBAL T* G(const T* p)
+{
+    return (const WAVE_GLOBAL T*)p;
+}
+
+template <class T>
+__device__ __forceinline__ WAVE_GLOBAL T* G(T* p)
+{
+    return (WAVE_GLOBAL T*)p;
+}
+
+// One injection entry read through a global-address-space pointer (member by
+// member: the implicit copy does not take an address-space-qualified source).
+__device__ __forceinline__ InjEntry load_entry(const InjEntry* ent, int64_t e)
+{
+    const WAVE_GLOBAL InjEntry* q = G(ent) + e;
+    InjEntry r;
+    r.z = q->z;
+    r.pt = q->pt;
+    r.w = q->w;
+    return r;
+}
+
 constexpr int kBlock = 256;
 
 template <int DIM>
-__device__ __forceinline__ float sample_point(const SampleSet& s, const float* __restrict__ u,
+__device__ __forceinline__ float sample_point(const SampleSet& s, const float* __restrict__ ug,
                                               int64_t p, int64_t sy, int64_t sx)
 {
-    const int64_t b = s.base[p];
-    const float* w = s.w + p * (1 << DIM);
+    const WAVE_GLOBAL float* u = G(ug);
+    const int64_t b = G(s.base)[p];
+    const WAVE_GLOBAL float* w = G(s.w) + p * (1 << DIM);
     float acc = 0.f;
     if (DIM == 2) {
         // corners (x, z): 00, 01, 10, 11
@@ -94,6 +133,18 @@ __device__ __forceinline__ void vstore(float* p, const Vec<VZ>& v)
     *reinterpret_cast<Vec<VZ>*>(p) = v;
 }
 
+template <int VZ>
+__device__ __forceinline__ Vec<VZ> vload(const WAVE_GLOBAL float* p)
+{
+    return *(const WAVE_GLOBAL Vec<VZ>*)p;
+}
+
+template <int VZ>
+__device__ __forceinline__ void vstore(WAVE_GLOBAL float* p, const Vec<VZ>& v)
+{
+    *(WAVE_GLOBAL Vec<VZ>*)p = v;
+}
+
 // Operands touched once per step (previous level, coefficients, output).
 // With NT they carry the non-temporal hint, which keeps them from evicting
 // wavefield planes that later tiles re-read; measured on gfx950 it pays only
@@ -101,15 +152,17 @@ __device__ __forceinline__ void vstore(float* p, const Vec<VZ>& v)
 template <int VZ, bool NT>
 __device__ __forceinline__ Vec<VZ> vload_once(const float* p)
 {
-    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const Vec<VZ>*>(p));
-    else return *reinterpret_cast<const Vec<VZ>*>(p);
+    const WAVE_GLOBAL Vec<VZ>* q = (const WAVE_GLOBAL Vec<VZ>*)p;
+    if constexpr (NT) return __builtin_nontemporal_load(q);
+    else return *q;
 }
 
 template <int VZ, bool NT>
 __device__ __forceinline__ void vstore_once(float* p, const Vec<VZ>& v)
 {
-    if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<Vec<VZ>*>(p));
-    else *reinterpret_cast<Vec<VZ>*>(p) = v;
+    WAVE_GLOBAL Vec<VZ>* q = (WAVE_GLOBAL Vec<VZ>*)p;
+    if constexpr (NT) __builtin_nontemporal_store(v, q);
+    else *q = v;
 }
 
 // Wait for this wave's LDS traffic, then meet the block at the barrier.
@@ -198,9 +251,9 @@ __device__ __forceinline__ void inject_core(const InjEntry* __restrict__ ent, co
 #pragma unroll
     for (int v = 0; v < VZ; ++v) { acc[v] = 0.f; hit[v] = false; }
     for (int32_t e = e0; e < e1; ++e) {
-        const InjEntry en = ent[e];
+        const InjEntry en = load_entry(ent, e);
         // w * val rounded, then added: the gathered values hold the same products
-        const float wv = ev ? ev[e] : en.w * val[en.pt];
+        const float wv = ev ? G(ev)[e] : en.w * G(val)[en.pt];
         const int64_t dz = (int64_t)en.z - z;
 #pragma unroll
         for (int v = 0; v < VZ; ++v)
@@ -317,7 +370,7 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, int64_t L)
         }
     }
 
-    const float* __restrict__ u = a.cur;
+    const WAVE_GLOBAL float* __restrict__ u = G(a.cur);
     auto center = [&](int64_t xx) -> Vec<VZ> {
         Vec<VZ> r = vzero<VZ>();
         if (own && xx >= 0 && xx < nx) r = vload<VZ>(u + xx * sx + col);
@@ -335,7 +388,7 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, int64_t L)
     // bit per plane in LDS, filled once), so that a plane's row lookup is a
     // per-row operand fetched ahead with the others instead of a dependent
     // load on every plane.
-    const int32_t* rp = a.inj.row_ptr;
+    const WAVE_GLOBAL int32_t* rp = G(a.inj.row_ptr);
     const bool inj_any = a.inj_val && xb > a.inj_x0 && xa <= a.inj_x1 &&
                          y0 + TY > a.inj_y0 && y0 <= a.inj_y1;
     __shared__ uint32_t inj_mask[kInjMaskWords];
@@ -421,11 +474,11 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, int64_t L)
         int32_t ez0 = -1, ez1 = -1;
         float ev0 = 0.f, ev1 = 0.f;
         if (inj_here && a.inj_ev) {
-            ez0 = a.inj.ent[P.e0].z;
-            ev0 = a.inj_ev[P.e0];
+            ez0 = G(a.inj.ent)[P.e0].z;
+            ev0 = G(a.inj_ev)[P.e0];
             if (P.e0 + 1 < P.e1) {
-                ez1 = a.inj.ent[P.e0 + 1].z;
-                ev1 = a.inj_ev[P.e0 + 1];
+                ez1 = G(a.inj.ent)[P.e0 + 1].z;
+                ev1 = G(a.inj_ev)[P.e0 + 1];
             }
         }
         if (i + PR - 1 < count) fetch(pre[(U + PR - 1) % PR], x + dir * (PR - 1));
@@ -508,8 +561,8 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, int64_t L)
                     if (ez1 >= 0 && ez1 - z == v) { acc[v] = acc[v] + ev1; hit[v] = true; }
                 }
                 for (int32_t e = P.e0 + 2; e < P.e1; ++e) {
-                    const int64_t dz = (int64_t)a.inj.ent[e].z - z;
-                    const float wv = a.inj_ev[e];
+                    const int64_t dz = (int64_t)G(a.inj.ent)[e].z - z;
+                    const float wv = G(a.inj_ev)[e];
 #pragma unroll
                     for (int v = 0; v < VZ; ++v)
                         if (dz == v) { acc[v] = acc[v] + wv; hit[v] = true; }
@@ -575,7 +628,7 @@ __device__ __forceinline__ void slab_body(const StepArgs& a, int64_t L)
     const int64_t xa = chunk * a.xchunk;
     const int64_t xb = xa + a.xchunk < nx ? xa + a.xchunk : nx;
     const int count = (int)(xb - xa);       // at most XR (planner)
-    const float* __restrict__ u = a.cur;
+    const WAVE_GLOBAL float* __restrict__ u = G(a.cur);
 
     // rows xa-R .. xb+R-1 of u^n with the z halo; zero outside the grid
     for (int i = tid; i < (count + 2 * R) * NV; i += NT) {
@@ -588,7 +641,7 @@ __device__ __forceinline__ void slab_body(const StepArgs& a, int64_t L)
     // rows of the chunk holding injected nodes: one flag per lane, one ballot
     // (a chunk has at most 64 rows), then each lane's entry range is fetched
     // with its other per-row operands
-    const int32_t* rp = a.inj.row_ptr;
+    const WAVE_GLOBAL int32_t* rp = G(a.inj.row_ptr);
     const bool inj_any = a.inj_val && xb > a.inj_x0 && xa <= a.inj_x1;
     uint64_t inj_rows = 0;
     if (inj_any) {
@@ -696,13 +749,13 @@ __global__ __launch_bounds__(TZL* TY, (step_waves_per_eu<DIM, VZ, IMG>())) void 
         const int64_t nsb = a.smp_out && a.smp.npts > 0 ? (a.smp.npts + TZL * TY - 1) / (TZL * TY) : 0;
         if (b - part < nsb) {
             const int64_t p = (b - part) * (TZL * TY) + threadIdx.x;
-            if (p < a.smp.npts) a.smp_out[p] = sample_point<DIM>(a.smp, a.cur, p, a.nz, a.ny * a.nz);
+            if (p < a.smp.npts) G(a.smp_out)[p] = sample_point<DIM>(a.smp, a.cur, p, a.nz, a.ny * a.nz);
         } else {
             // gather of the next step's injection values into entry order
             const int64_t e = (b - part - nsb) * (TZL * TY) + threadIdx.x;
             if (e < a.nent) {
-                const InjEntry en = a.inj.ent[e];
-                a.ev_out[e] = en.w * a.ev_src[en.pt];
+                const InjEntry en = load_entry(a.inj.ent, e);
+                G(a.ev_out)[e] = en.w * G(a.ev_src)[en.pt];
             }
         }
         return;
@@ -743,7 +796,7 @@ __global__ __launch_bounds__(TZL* TY) void k_step_batch(const ShotDesc* __restri
     const int64_t lb = b - begin[lo];
     if (lb >= a.stencil_blocks) {
         const int64_t p = (lb - a.stencil_blocks) * (TZL * TY) + threadIdx.x;
-        if (p < a.smp.npts && a.smp_out) a.smp_out[p] = sample_point<DIM>(a.smp, a.cur, p, a.nz, a.ny * a.nz);
+        if (p < a.smp.npts && a.smp_out) G(a.smp_out)[p] = sample_point<DIM>(a.smp, a.cur, p, a.nz, a.ny * a.nz);
         return;
     }
     stream_tile<DIM, R, VZ, TZL, TY, false>(a, lb);
@@ -786,7 +839,7 @@ __global__ __launch_bounds__(TZL* TY) void k_batch_persistent(const ShotDesc* __
             if (lb >= a.stencil_blocks) {
                 const int64_t p = (lb - a.stencil_blocks) * (TZL * TY) + threadIdx.x;
                 if (p < a.smp.npts && a.smp_out)
-                    a.smp_out[p] = sample_point<DIM>(a.smp, a.cur, p, a.nz, a.ny * a.nz);
+                    G(a.smp_out)[p] = sample_point<DIM>(a.smp, a.cur, p, a.nz, a.ny * a.nz);
             } else {
                 stream_tile<DIM, R, VZ, TZL, TY, false>(a, lb);
             }
@@ -821,107 +874,104 @@ __global__ __launch_bounds__(TZL* TY) void k_batch_persistent(const ShotDesc* __
 }
 
 // Two time steps per pass (temporal blocking, 2D): levels n+1 and n+2 from
-// u^n and u^{n-1} in one read of the fields.  A block of eight waves owns
-// TZO = 256 - 2 RZ z-points over an x-chunk of at most kSlab2Rows rows; its
-// lanes cover the owned z plus RZ on either side.
-//   1. rows xa-2R .. xb+2R-1 of u^n (z halo RZ beyond the lanes) go to LDS;
-//      u^{n-1}, alpha and beta of rows xa-R .. xb+R-1 to registers;
-//   2. step 1 computes u^{n+1} on rows xa-R .. xb+R-1 at every lane (zero
-//      outside the grid), with the level-n injection; the owned part goes to
-//      `out1`;
-//   3. after a barrier the block overwrites u^n in LDS with u^{n+1} (u^n of
-//      its own points stays in registers);
-//   4. step 2 computes u^{n+2} on the owned rows and lanes, with the level
-//      n+1 injection, into `a.out`.
+// u^n and u^{n-1} with one read of the fields.  A block of XR waves owns
+// TZO = 256 - 2 RZ z-points of a column of x-rows [X0, X1); its lanes cover
+// the owned z plus RZ on either side.  It walks the column in rounds of XR
+// rows:
+//   - u^n rows enter a ring in LDS (z halo RZ beyond the lanes), fetched one
+//     round ahead into registers; level n+1 rows enter a second ring;
+//   - step 1 of round j computes level n+1 on rows X0 + R + XR j + [0, XR)
+//     (before the first round, on the 2R rows around X0), at every lane,
+//     zero outside the grid, with the level-n injection; rows inside
+//     [X0, X1) at the owned lanes also go to `out1`;
+//   - step 2 of round j computes level n+2 on the rows step 1 produced in
+//     the previous round, with the level n+1 injection, into `a.out`.
+// Wave w takes the rows congruent to w (mod XR) relative to X0 in both
+// steps, so the coefficients a row's step 1 loaded serve its step 2 a round
+// later from registers.
 // Each point's arithmetic is that of the single step (same operations in the
 // same order), and a point outside the block's own part is computed from the
 // same inputs as by the block that owns it, so two steps here are bitwise two
-// single steps.  The inputs are not written during the pass, which is why the
-// outputs go to a second pair of buffers: 20 + 4 (4R/XR) + 12 (2R/XR) + 4 B
-// read and written per two updates instead of 2 x (20 + 4 (2R/XR)).
-template <int R, int VZ, int TZL, int TW>
-__device__ __forceinline__ void slab2_body(const StepArgs& a, int64_t L, const float* __restrict__ val0,
+// single steps.  The inputs are not written during the pass, so the outputs
+// go to a second pair of buffers.  Per own point and pass the block reads
+// u^n (1 + 4R/C) times and u^{n-1}, alpha, beta (1 + 2R/C) times for a
+// column of C rows, and writes two levels: 24 B per two updates as C grows,
+// against 2 x 20 B for single steps.  Loads are issued in the order they
+// are consumed, so no wait for one also waits for a later one.
+template <int R, int VZ, int TZL, int XR>
+__device__ __forceinline__ void roll2_body(const StepArgs& a, int64_t L, const float* __restrict__ val0,
                                            const float* __restrict__ val1, float* __restrict__ out1,
                                            bool two)
 {
-    constexpr int NT = TZL * TW;
+    constexpr int NT = TZL * XR;                   // one wave per row of a round
     constexpr int RZ = (R + VZ - 1) / VZ * VZ;
     constexpr int TZE = TZL * VZ;                  // z the lanes cover
     constexpr int TZO = TZE - 2 * RZ;              // z a block owns
-    constexpr int PITCH = TZE + 2 * RZ;
-    constexpr int XR = kSlab2Rows, NE = XR + 2 * R, ROWS = XR + 4 * R, NV = PITCH / VZ;
-    constexpr int S = (NE + TW - 1) / TW;          // step-1 rows per wave
-    static_assert(NE <= 64, "the injection rows of a chunk are one wave-wide ballot");
-    static_assert(TZL % 64 == 0, "one wave per row group keeps the row test uniform");
+    constexpr int P = TZE + 2 * RZ;                // row pitch of both rings
+    // rows held: u^n from the oldest row a step 2 still reads to the newest
+    // prefetched one (and the prologue's 4R rows plus one round); level n+1
+    // from the oldest row a step 2 reads to the newest step-1 row
+    constexpr int RING1 = (R + 3 * XR > 4 * R + XR) ? R + 3 * XR : 4 * R + XR;
+    constexpr int RING2 = R + 2 * XR;
+    constexpr int NV = P / VZ;                     // vectors per u^n row
+    constexpr int NPV = (XR * NV + NT - 1) / NT;   // u^n vectors per thread per round
+    static_assert(R <= XR, "step 2 lags step 1 by one round");
+    static_assert(TZL % 64 == 0, "one wave per row keeps the row tests uniform");
     static_assert(TZO > 0 && TZO % VZ == 0, "owned z must be whole vectors");
-    __shared__ __attribute__((aligned(16))) float lds[ROWS * PITCH];
+    __shared__ __attribute__((aligned(16))) float ring1[RING1 * P];
+    __shared__ __attribute__((aligned(16))) float ring2[RING2 * P];
 
     const int64_t nx = a.nx, nz = a.nz;
     const int tid = threadIdx.x;
     const int tzi = (int)(L % a.ntz);
-    const int64_t chunk = L / a.ntz;
-    const int tz = tid % TZL, tw = tid / TZL;
+    const int64_t col = L / a.ntz;
+    // the wave index is uniform: row arithmetic then stays scalar
+    const int tz = tid % TZL, w = __builtin_amdgcn_readfirstlane(tid / TZL);
     const int64_t z0 = (int64_t)tzi * TZO;         // first owned z
     const int64_t z = z0 - RZ + (int64_t)tz * VZ;  // the lane's first point
     // nz and z are multiples of VZ: a lane's points are all inside or all out
     const bool zin = z >= 0 && z < nz;
     const bool zown = zin && tz >= RZ / VZ && tz < TZL - RZ / VZ;
-    const int64_t xa = chunk * a.xchunk;
-    const int64_t xb = xa + a.xchunk < nx ? xa + a.xchunk : nx;
-    const int count = (int)(xb - xa);              // at most XR (planner)
-    const int ne = count + 2 * R;
-
-    for (int i = tid; i < (count + 4 * R) * NV; i += NT) {
-        const int r = i / NV, k = i - r * NV;
-        const int64_t xx = xa - 2 * R + r, zz = z0 - 2 * RZ + (int64_t)k * VZ;
+    const int64_t X0 = col * a.xchunk;
+    const int64_t X1 = X0 + a.xchunk < nx ? X0 + a.xchunk : nx;
+    const int64_t base1 = X0 - 2 * R, base2 = X0 - R;   // rows of slot 0 (rows are never below)
+    const int lane_off = RZ + tz * VZ;
+    auto row1 = [&](int64_t r) { return ring1 + (int)((uint32_t)(r - base1) % RING1) * P + lane_off; };
+    auto row2 = [&](int64_t r) { return ring2 + (int)((uint32_t)(r - base2) % RING2) * P + lane_off; };
+    auto unload = [&](int64_t r, int k) {         // vector k of u^n row r (zero outside the grid)
+        const int64_t zz = z0 - 2 * RZ + (int64_t)k * VZ;
         Vec<VZ> v = vzero<VZ>();
-        if (xx >= 0 && xx < nx && zz >= 0 && zz < nz) v = vload<VZ>(a.cur + xx * nz + zz);
-        vstore<VZ>(lds + r * PITCH + k * VZ, v);
-    }
-    // rows of the widened chunk that hold injected nodes (one ballot)
-    const int32_t* rp = a.inj.row_ptr;
-    const bool inj_any = val0 && xb + R > a.inj_x0 && xa - R <= a.inj_x1;
-    uint64_t inj_rows = 0;
-    if (inj_any) {
-        const int lane = tid & 63;
-        const int64_t x = xa - R + lane;
-        inj_rows = __ballot(lane < ne && x >= 0 && x < nx && rp[x + 1] != rp[x]);
-    }
-    Vec<VZ> uo[S], al[S], be[S];
-    int32_t e0[S], e1[S];
-#pragma unroll
-    for (int k = 0; k < S; ++k) {
-        const int r = tw + k * TW;
-        const int64_t x = xa - R + r;
-        const bool in = r < ne && x >= 0 && x < nx && zin;
-        e0[k] = e1[k] = 0;
-        if (in && ((inj_rows >> r) & 1u)) {
-            e0[k] = rp[x];
-            e1[k] = rp[x + 1];
+        if (r >= 0 && r < nx && zz >= 0 && zz < nz) v = vload<VZ>(G(a.cur) + r * nz + zz);
+        return v;
+    };
+    const WAVE_GLOBAL int32_t* rp = G(a.inj.row_ptr);
+    const bool inj_any = val0 && X1 + R > a.inj_x0 && X0 - R <= a.inj_x1;
+    auto inj_range = [&](int64_t x, int32_t& e0, int32_t& e1) {   // x uniform per wave
+        e0 = e1 = 0;
+        if (inj_any && x >= a.inj_x0 && x <= a.inj_x1 && x >= 0 && x < nx) {
+            e0 = rp[x];
+            e1 = rp[x + 1];
         }
-        uo[k] = al[k] = be[k] = vzero<VZ>();
-        if (in) {
+    };
+    // step-1 operands of row x (zero outside the grid)
+    struct Ops {
+        Vec<VZ> uo, al, be;
+        int32_t e0, e1;
+    };
+    auto fetch_ops = [&](int64_t x, Ops& o) {
+        o.uo = o.al = o.be = vzero<VZ>();
+        inj_range(x, o.e0, o.e1);
+        if (x >= 0 && x < nx && zin) {
             const int64_t off = x * nz + z;
             if (!a.no_prev) {
-                uo[k] = vload<VZ>(a.other + off);
-                be[k] = vload<VZ>(a.beta + off);
+                o.uo = vload<VZ>(G(a.other) + off);
+                o.be = vload<VZ>(G(a.beta) + off);
             }
-            al[k] = vload<VZ>(a.alpha + off);
+            o.al = vload<VZ>(G(a.alpha) + off);
         }
-    }
-    __syncthreads();
-
-    // step 1: u^{n+1} on the widened rows
-    Vec<VZ> o1[S], cc[S];
-#pragma unroll
-    for (int k = 0; k < S; ++k) {
-        const int r = tw + k * TW;
-        o1[k] = cc[k] = vzero<VZ>();
-        if (r >= ne) continue;                     // uniform within a wave
-        const int64_t x = xa - R + r;
-        const float* Lc = lds + (r + R) * PITCH + RZ + tz * VZ;
-        const Vec<VZ> c = vload<VZ>(Lc);
-        float lap[VZ], m2c[VZ];
+    };
+    // Laplacian of the lane's points of row x from a ring
+    auto laplace = [&](auto row, int64_t x, const Vec<VZ>& c, float* lap, float* m2c) {
 #pragma unroll
         for (int v = 0; v < VZ; ++v) {
             lap[v] = 0.f;
@@ -929,59 +979,104 @@ __device__ __forceinline__ void slab2_body(const StepArgs& a, int64_t L, const f
         }
 #pragma unroll
         for (int j = 1; j <= R; ++j) {
-            const Vec<VZ> p = vload<VZ>(Lc + j * PITCH);
-            const Vec<VZ> m = vload<VZ>(Lc - j * PITCH);
+            const Vec<VZ> p = vload<VZ>(row(x + j));
+            const Vec<VZ> m = vload<VZ>(row(x - j));
 #pragma unroll
             for (int v = 0; v < VZ; ++v) lap[v] = fmaf(a.cx[j], (p[v] + m[v]) + m2c[v], lap[v]);
         }
-        z_terms<R, VZ, RZ>(Lc, c, m2c, a.cz, lap);
-        Vec<VZ> o = update_core<VZ>(c, lap, uo[k], al[k], be[k]);
-        if (e1[k] > e0[k]) inject_core<VZ>(a.inj.ent, nullptr, val0, e0[k], e1[k], z, al[k], o);
-        if (x >= 0 && x < nx && zin) {
-            o1[k] = o;
-            cc[k] = c;
-            if (zown && r >= R && r < R + count) vstore<VZ>(out1 + x * nz + z, o);
-        }
-    }
-    if (!two) return;                              // one step only (uniform)
-    __syncthreads();                               // every wave is done with u^n in LDS
-#pragma unroll
-    for (int k = 0; k < S; ++k) {
-        const int r = tw + k * TW;
-        if (r < ne) vstore<VZ>(lds + (r + R) * PITCH + RZ + tz * VZ, o1[k]);
-    }
-    __syncthreads();
-
-    // step 2: u^{n+2} on the owned rows
-#pragma unroll
-    for (int k = 0; k < S; ++k) {
-        const int r = tw + k * TW;
-        if (r >= ne) break;                        // uniform within a wave
-        if (r < R || r >= R + count) continue;
-        const int64_t x = xa - R + r;
-        const float* Lc = lds + (r + R) * PITCH + RZ + tz * VZ;
-        const Vec<VZ> c = vload<VZ>(Lc);
+        z_terms<R, VZ, RZ>(row(x), c, m2c, a.cz, lap);
+    };
+    // level n+1 of row x into ring 2 (zero outside the grid) and, inside
+    // [X0, X1) at the owned lanes, into out1
+    auto step1 = [&](int64_t x, const Ops& q) {
+        const Vec<VZ> c = vload<VZ>(row1(x));
         float lap[VZ], m2c[VZ];
+        laplace(row1, x, c, lap, m2c);
+        Vec<VZ> o = update_core<VZ>(c, lap, q.uo, q.al, q.be);
+        if (q.e1 > q.e0) inject_core<VZ>(a.inj.ent, nullptr, val0, q.e0, q.e1, z, q.al, o);
+        const bool in = x >= 0 && x < nx && zin;
+        vstore<VZ>(row2(x), in ? o : vzero<VZ>());
+        if (in && zown && x >= X0 && x < X1) vstore<VZ>(G(out1) + x * nz + z, o);
+    };
+    // level n+2 of row x (in [X0, X1)) with its step-1 coefficients
+    auto step2 = [&](int64_t x, const Ops& q) {
+        const Vec<VZ> c = vload<VZ>(row2(x));
+        float lap[VZ], m2c[VZ];
+        laplace(row2, x, c, lap, m2c);
+        const Vec<VZ> un0 = vload<VZ>(row1(x));    // u^n of the point
+        Vec<VZ> o = update_core<VZ>(c, lap, un0, q.al, q.be);
+        if (q.e1 > q.e0) inject_core<VZ>(a.inj.ent, nullptr, val1, q.e0, q.e1, z, q.al, o);
+        if (zown) vstore<VZ>(G(a.out) + x * nz + z, o);
+    };
+
+    // prologue: u^n rows [X0-2R, X0+2R) straight into the ring, the first
+    // round's rows into registers, the step-1 operands of this wave's rows
+    // among [X0-R, X0+R): X0 + w - XR (when >= X0 - R) and X0 + w (when < X0 + R)
+    for (int i = tid; i < 4 * R * NV; i += NT) {
+        const int r = i / NV, k = i - r * NV;
+        vstore<VZ>(ring1 + r * P + k * VZ, unload(base1 + r, k));
+    }
+    const int64_t ulim = X1 + 2 * R;               // u^n rows needed end here
+    // the XR u^n rows from row un: into registers, and from there into the ring
+    auto fetch_u = [&](Vec<VZ>* pv, int64_t un) {
 #pragma unroll
-        for (int v = 0; v < VZ; ++v) {
-            lap[v] = 0.f;
-            m2c[v] = -2.f * c[v];
+        for (int m = 0; m < NPV; ++m) {
+            const int i = tid + m * NT;
+            const int r = i / NV, k = i - r * NV;
+            pv[m] = (i < XR * NV && un + r < ulim) ? unload(un + r, k) : vzero<VZ>();
         }
+    };
+    auto store_u = [&](const Vec<VZ>* pv, int64_t un) {
 #pragma unroll
-        for (int j = 1; j <= R; ++j) {
-            const Vec<VZ> p = vload<VZ>(Lc + j * PITCH);
-            const Vec<VZ> m = vload<VZ>(Lc - j * PITCH);
-#pragma unroll
-            for (int v = 0; v < VZ; ++v) lap[v] = fmaf(a.cx[j], (p[v] + m[v]) + m2c[v], lap[v]);
+        for (int m = 0; m < NPV; ++m) {
+            const int i = tid + m * NT;
+            const int r = i / NV, k = i - r * NV;
+            if (i < XR * NV) vstore<VZ>(row1(un + r) - lane_off + k * VZ, pv[m]);
         }
-        z_terms<R, VZ, RZ>(Lc, c, m2c, a.cz, lap);
-        Vec<VZ> o = update_core<VZ>(c, lap, cc[k], al[k], be[k]);
-        if (e1[k] > e0[k]) inject_core<VZ>(a.inj.ent, nullptr, val1, e0[k], e1[k], z, al[k], o);
-        if (zown) vstore<VZ>(a.out + x * nz + z, o);
+    };
+    int64_t un = X0 + 2 * R;                       // next u^n rows to prefetch
+    Vec<VZ> pv[NPV];
+    fetch_u(pv, un);
+    const int64_t xa = X0 + w - XR, xb = X0 + w;   // this wave's prologue rows
+    const bool has_a = w >= XR - R, has_b = w < R;
+    Ops qa, q, carry;
+    if (has_a) fetch_ops(xa, qa);
+    if (has_b) fetch_ops(xb, q);
+    lds_barrier();                                 // prologue rows in the ring
+    if (has_a) step1(xa, qa);
+    if (has_b) step1(xb, q);
+    // step 2 of the next round takes row xb (when inside the column)
+    bool has2 = has_b && xb < X1;
+    int64_t x2 = xb;
+    carry = q;
+    const int64_t lim1 = X1 + R;                   // step-1 rows needed end here
+    int64_t x1 = X0 + R + (int64_t)((w - R + XR) % XR);   // this wave's row of round 0
+    if (x1 < lim1) fetch_ops(x1, q);
+    const int rounds = (int)((X1 - X0 + XR - 1) / XR);      // step-1 rounds; one more for step 2
+    for (int j = 0; j <= rounds; ++j) {
+        if (j < rounds) {
+            store_u(pv, un);                       // slots of rows no wave reads any more
+            un += XR;
+            if (un < ulim) fetch_u(pv, un);
+        }
+        lds_barrier();                             // u^n rows in; the last step 2 is done with ring 2
+        const bool act1 = j < rounds && x1 < lim1;
+        if (act1) step1(x1, q);
+        const Ops next = q;                        // its coefficients serve step 2 next round
+        const bool next2 = act1 && x1 < X1;
+        const int64_t nx2 = x1;
+        x1 += XR;
+        if (j + 1 < rounds && x1 < lim1) fetch_ops(x1, q);
+        if (!two) continue;                        // uniform: a one-step launch
+        lds_barrier();                             // level n+1 rows in
+        if (has2) step2(x2, carry);
+        has2 = next2;
+        x2 = nx2;
+        carry = next;
     }
 }
 
-// Two steps of every shot in one launch (2D, the slab2 body): levels n+1 and
+// Two steps of every shot in one launch (2D, the rolling two-step body): levels n+1 and
 // n+2 from buffers buf[bufs & 3] (u^n) and buf[(bufs >> 2) & 3] (u^{n-1})
 // into buf[(bufs >> 4) & 3] (u^{n+1}) and buf[(bufs >> 6) & 3] (u^{n+2}),
 // with the injection rows n and n+1.  Blocks past a shot's tiles sample
@@ -990,7 +1085,7 @@ __device__ __forceinline__ void slab2_body(const StepArgs& a, int64_t L, const f
 // last pass); with flags & 8 the tiles take one step only (u^{n+1} into
 // buf[(bufs >> 4) & 3]), which starts a run with an odd number of steps.
 template <int R>
-__global__ __launch_bounds__(kSlab2Threads) void k_step_batch2(const ShotDesc* __restrict__ shots,
+__global__ __launch_bounds__(kSlab2Threads, WAVE_SLAB2_WPE) void k_step_batch2(const ShotDesc* __restrict__ shots,
                                                                const int64_t* __restrict__ begin,
                                                                int32_t nshots, int32_t n, int32_t bufs,
                                                                int32_t flags)
@@ -1007,26 +1102,34 @@ __global__ __launch_bounds__(kSlab2Threads) void k_step_batch2(const ShotDesc* _
     StepArgs a = D.a;
     const float* u0 = D.buf[bufs & 3];
     const float* um = D.buf[(bufs >> 2) & 3];
-    const int64_t lb = b - begin[lo];
-    if (lb >= a.stencil_blocks) {
+    WAVE_GLOBAL float* d = G(D.d);
+    int64_t lb = b - begin[lo];
+    const int64_t part = a.remap ? (a.stencil_blocks + 7) / 8 * 8 : a.stencil_blocks;
+    if (lb >= part) {
         const int64_t nsb = (a.smp.npts + NT - 1) / NT;
-        const int64_t sb = lb - a.stencil_blocks;
+        const int64_t sb = lb - part;
         const bool second = sb >= nsb;
         const int64_t p = (second ? sb - nsb : sb) * NT + threadIdx.x;
-        if (p < a.smp.npts && D.d) {
-            if (!second && (flags & 2)) D.d[(int64_t)n * D.nrec + p] = sample_point<2>(a.smp, u0, p, a.nz, a.nz);
+        if (p < a.smp.npts && d) {
+            if (!second && (flags & 2)) d[(int64_t)n * D.nrec + p] = sample_point<2>(a.smp, u0, p, a.nz, a.nz);
             if (second && (flags & 4) && n >= 1)
-                D.d[(int64_t)(n - 1) * D.nrec + p] = sample_point<2>(a.smp, um, p, a.nz, a.nz);
+                d[(int64_t)(n - 1) * D.nrec + p] = sample_point<2>(a.smp, um, p, a.nz, a.nz);
         }
         return;
     }
     if (!(flags & 1)) return;
+    if (a.remap) {
+        // shots start at multiples of 8 blocks, so lb & 7 is the XCD: each
+        // XCD takes a contiguous run of tiles (x-neighbours share its L2)
+        lb = (lb & 7) * (part >> 3) + (lb >> 3);
+        if (lb >= a.stencil_blocks) return;
+    }
     a.cur = u0;
     a.other = um;
     a.out = D.buf[(bufs >> 6) & 3];
     const float* v0 = D.nsrc ? D.q + (int64_t)n * D.nsrc : nullptr;
     const float* v1 = D.nsrc ? D.q + (int64_t)(n + 1) * D.nsrc : nullptr;
-    slab2_body<R, 4, 64, kSlab2Threads / 64>(a, lb, v0, v1, D.buf[(bufs >> 4) & 3], !(flags & 8));
+    roll2_body<R, 4, 64, kSlab2Threads / 64>(a, lb, v0, v1, D.buf[(bufs >> 4) & 3], !(flags & 8));
 }
 
 template <int DIM_, int R_, int VZ_, int TZL_, int TY_>
@@ -1128,8 +1231,9 @@ int64_t plan_t(StepArgs& a, int xchunk, int64_t resident = 0, bool single = fals
     return part + nsb + ngb;
 }
 
-// Plan of the two-step slab (2D): tiles of 256 - 2 RZ owned z, x-chunks of
-// at most kSlab2Rows rows; two sampler groups per shot (u^n and u^{n-1}).
+// Plan of the two-step body (2D): tiles of 256 - 2 RZ owned z, columns of
+// `xchunk` rows (default kSlab2Column); two sampler groups per shot (u^n and
+// u^{n-1}).
 template <int R>
 int64_t plan_t2(StepArgs& a, int xchunk)
 {
@@ -1138,15 +1242,16 @@ int64_t plan_t2(StepArgs& a, int xchunk)
     if (a.nz % 4 != 0) return -1;
     a.ntz = (int32_t)((a.nz + TZO - 1) / TZO);
     a.nty = 1;
-    if (xchunk <= 0 || xchunk > kSlab2Rows) xchunk = kSlab2Rows;
+    if (xchunk <= 0) xchunk = kSlab2Column;
     if (xchunk > a.nx) xchunk = (int)a.nx;
     a.xchunk = xchunk;
     const int64_t nchunk = (a.nx + xchunk - 1) / xchunk;
     a.stencil_blocks = (int64_t)a.ntz * nchunk;
-    a.remap = 0;
+    a.remap = WAVE_BATCH2_REMAP;
+    const int64_t part = a.remap ? (a.stencil_blocks + 7) / 8 * 8 : a.stencil_blocks;
     int64_t nsb = 0;
     if (a.smp_out && a.smp.npts > 0) nsb = 2 * ((a.smp.npts + kSlab2Threads - 1) / kSlab2Threads);
-    return a.stencil_blocks + nsb;
+    return part + nsb;
 }
 
 // Zero fill (the persistent graph clears its barrier words with it: a kernel

@@ -14,8 +14,8 @@ Workloads (seeded synthetic layered models, sponge, Ricker source):
               run, with its own roofline block)
 Further legs of the default run: the FWI gradient (200^3, checkpointed,
 FP32/BF16/FP16 snapshots) against the plain forward, 48 batched 2D shots
-against the single-shot path, the paper's diffusion example, and the CPU
-oracle on a bounded sample.
+against the single-shot path (with the batch kernel's own roofline block),
+the paper's diffusion example, and the CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -173,20 +173,27 @@ def gradient_bench(dev, reps=2):
     return out
 
 
-def batched_bench(dev, reps=2):
+BYTES_PER_PASS = 24       # two-step pass: read u^n, u^{n-1}, alpha, beta; write two levels
+
+
+def batched_bench(dev, reps=2, nt=0, full=True, tile=0):
     """48 2D shots of uneven aperture on a 2001 x 801 layered model, order 8,
-    2000 steps, one launch per step over all shots replayed from a hipGraph,
-    tile chosen by the autotuner; against the single-shot order-8 2D kernel
-    on the full 2001 x 801 model."""
+    2000 steps, launches over all shots replayed from a hipGraph, tile chosen
+    by the autotuner (the two-step body advances two levels per launch);
+    against the single-shot order-8 2D kernel on the full 2001 x 801 model.
+    The roofline block prices the batch kernel's average launch (HIP events
+    around the time loop inside the library) at its algorithmic bytes."""
     import torch
-    from paper_1609_03361_amd import api, synth
-    probs = synth.config_batched_2d()
+    from paper_1609_03361_amd import api, synth, _lib
+    probs = synth.config_batched_2d(nt=nt) if nt > 0 else synth.config_batched_2d()
     shots = []
     for p in probs:
         geom = api.Geometry(p.shape, p.spacing, p.order, p.dt, p.nt, p.src, p.rec)
         shots.append((geom, torch.from_numpy(p.m).to(dev), torch.from_numpy(p.eta).to(dev),
                       torch.from_numpy(p.q).to(dev)))
-    tile, tune_us = api.tune_batch(shots, steps=10)
+    tune_us = None
+    if tile == 0:
+        tile, tune_us = api.tune_batch(shots, steps=10)
     pts = sum(p.npoints for p in probs) * probs[0].nt
 
     def timed(fn, reps=reps):
@@ -201,6 +208,27 @@ def batched_bench(dev, reps=2):
         return best
 
     tb = timed(lambda: api.forward_batch(shots, tile=tile))
+    # one more run with the library's loop events: the average launch
+    _lib.set_profiling(True)
+    api.forward_batch(shots, tile=tile)
+    loop_ms, launches = _lib.last_loop()
+    _lib.set_profiling(False)
+    two = (tile >> 16) == 4
+    npts = sum(p.npoints for p in probs)
+    passes = probs[0].nt // 2 if two else probs[0].nt
+    per_launch_ms = loop_ms / passes     # two-step: the launches that advance two levels
+    alg = (BYTES_PER_PASS if two else BYTES_PER_UPDATE) * npts
+    achieved = alg / (per_launch_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            # counters were taken on the two-step body with columns of 64 rows
+            "traffic": measured_traffic("batch2d-o8") if tile == (4 << 16 | 64) and nt == 0 else None,
+            "kernel": "two-step pass (levels n+1, n+2)" if two else "leapfrog step",
+            "launch_ms": round(per_launch_ms, 5), "alg_bytes_per_launch": alg,
+            "launches_in_loop": launches}
+    if not full:
+        return {"batched_gpts": round(pts / tb / 1e9, 2), "batched_s": round(tb, 4),
+                "tile": {"variant": tile >> 16, "xchunk": tile & 0xffff}, "roofline": roof}
     tp = timed(lambda: api.forward_batch(shots, tile=tile, persistent=True), reps=1)
     # the same model as one shot, through the single-shot path
     m_full, _ = synth.layered((2001, 801), 4)
@@ -217,9 +245,12 @@ def batched_bench(dev, reps=2):
     return {"workload": f"{len(probs)} 2D shots, widths {min(p.shape[0] for p in probs)}-"
                         f"{max(p.shape[0] for p in probs)} x 801, order 8, {p0.nt} steps",
             "batched_gpts": round(batched, 2), "batched_s": round(tb, 4),
-            "mode": "per-step launches over all shots, replayed from a hipGraph",
+            "mode": ("two-step launches (levels n+1, n+2) over all shots" if two else
+                     "per-step launches over all shots") + ", replayed from a hipGraph",
             "persistent_single_launch_s": round(tp, 4),
-            "tile": {"variant": tile >> 16, "xchunk": tile & 0xffff, "tuned_us_per_step": round(tune_us, 2)},
+            "tile": {"variant": tile >> 16, "xchunk": tile & 0xffff,
+                     "tuned_us_per_step": None if tune_us is None else round(tune_us, 2)},
+            "roofline": roof,
             "persistent_mode": api.last_batch_mode(),
             "single_shot_full_model_gpts": round(single, 2),
             "batched_vs_single": round(batched / single, 3)}
@@ -263,12 +294,20 @@ def main():
     ap.add_argument("--nt", type=int, default=0,
                     help="override the number of time steps (for short profiler runs)")
     ap.add_argument("--tile", type=int, default=0,
-                    help="tile id of the main leg (variant << 16 | x-chunk; 0 = tuned or automatic)")
+                    help="tile id of the main leg, or with --only-batched of the batch "
+                         "(variant << 16 | x-chunk; 0 = tuned or automatic)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 10 times (HBM counter calibration)")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="only time the batched shots (with --nt for short profiler runs)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.only_batched:
+        import torch
+        print(json.dumps({"batched_shots": batched_bench(torch.device("cuda:0"), nt=args.nt,
+                                                         full=False, tile=args.tile)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs on a single MI355X and has no "

@@ -504,8 +504,11 @@ TileCfg cached_tile(const std::string& key, const Geo& G, bool batch)
 }
 
 // opts->tile: 0 = cached or default, else an explicit id that must name an
-// existing block shape (the two-step 2D slab only where `batch`).
-int pick_tile(const wave_opts* o, const std::string& key, const Geo& G, TileCfg* out, bool batch = false)
+// existing block shape.  The two-step 2D body is accepted where `two_step`
+// (the batched forward, and the single-shot forward without checkpoints),
+// and is the default of the batched forward (`batch`).
+int pick_tile(const wave_opts* o, const std::string& key, const Geo& G, TileCfg* out, bool batch = false,
+              bool two_step = false)
 {
     if (o->tile < 0) return fail(WAVE_EINVAL, "tile id %d is negative", o->tile);
     if (o->tile == 0) {
@@ -513,14 +516,15 @@ int pick_tile(const wave_opts* o, const std::string& key, const Geo& G, TileCfg*
         return WAVE_OK;
     }
     const TileCfg c = tile_from_id(o->tile);
-    if (batch && G.ndim == 2 && c.variant == kTwoStepVariant) {
+    if ((batch || two_step) && G.ndim == 2 && c.variant == kTwoStepVariant) {
         *out = c;
         return WAVE_OK;
     }
     if (c.variant >= tile_variants(G.ndim, G.nzp))
         return fail(WAVE_EINVAL, "tile variant %d does not exist (%dD has %d%s)", c.variant, G.ndim,
                     tile_variants(G.ndim, G.nzp),
-                    G.ndim == 2 ? "; the two-step variant 4 runs in wave_forward_batch only" : "");
+                    G.ndim == 2 ? "; the two-step variant 4 runs in wave_forward_batch and in "
+                                  "wave_forward without checkpoints only" : "");
     *out = c;
     return WAVE_OK;
 }
@@ -1012,6 +1016,25 @@ int batch_plan(int32_t nshots, const wave_shot* shots, BatchPlan* B, bool build_
     return WAVE_OK;
 }
 
+// Workspace of a batch of one shot with ns sources and nr receivers (the
+// single-shot 2D forward on the two-step body runs as one); batch_plan only
+// checks the pointers for presence here, it reads no data.
+size_t one_shot_batch_bytes(const wave_grid& grid, int ns, int nr)
+{
+    static const float present = 0.f;
+    wave_shot one;
+    std::memset(&one, 0, sizeof one);
+    one.grid = grid;
+    one.m = &present;
+    one.src.npts = ns;
+    one.rec.npts = nr;
+    one.q = &present;
+    one.d = const_cast<float*>(&present);
+    BatchPlan B;
+    if (batch_plan(1, &one, &B, false)) return 0;
+    return B.total;
+}
+
 StepArgs shot_args(const BatchShot& S, char* ws)
 {
     StepArgs a;
@@ -1066,8 +1089,6 @@ void build_descs(const BatchPlan& B, const wave_shot* shots, char* ws, TileCfg c
         D.d = S.rec.npts ? shots[i].d : nullptr;
         D.nsrc = S.src.npts;
         D.nrec = S.rec.npts;
-        // a remapped plan needs its shot to start at a multiple of 8 blocks
-        if (D.a.remap) acc = (acc + 7) / 8 * 8;
         (*begin)[k] = acc;
         acc += nb;
     }
@@ -1393,7 +1414,7 @@ int wave_resolve_tile(const wave_grid* grid, int32_t tile, int32_t* resolved)
         std::memset(&o, 0, sizeof o);
         o.tile = tile;
         TileCfg cfg;
-        if ((rc = pick_tile(&o, tune_key(G, false), G, &cfg))) return rc;
+        if ((rc = pick_tile(&o, tune_key(G, false), G, &cfg, false, true))) return rc;
         StepArgs a;
         std::memset(&a, 0, sizeof a);
         a.nx = G.n[0]; a.ny = G.n[1]; a.nz = G.nzp;
@@ -1458,6 +1479,7 @@ int wave_workspace_size(int32_t op, const wave_grid* grid, const wave_points* sr
         const int ns = src ? src->npts : 0, nr = rec ? rec->npts : 0;
         if (ns < 0 || nr < 0) return fail(WAVE_EINVAL, "npts < 0");
         *bytes = make_plan(op, G, ns, nr, opts).total;
+        if (op == WAVE_OP_FORWARD && G.ndim == 2) *bytes = std::max(*bytes, one_shot_batch_bytes(*grid, ns, nr));
         return WAVE_OK;
     } catch (const std::exception& e) {
         return fail(WAVE_EINVAL, "exception: %s", e.what());
@@ -1487,6 +1509,23 @@ int wave_forward(const wave_grid* grid, const float* m, const float* eta, const 
         const int op = ckpt ? WAVE_OP_FORWARD_CKPT : WAVE_OP_FORWARD;
         if (src && src->npts > 0 && !q) return fail(WAVE_EINVAL, "q is NULL with %d sources", src->npts);
         if (rec && rec->npts > 0 && !d) return fail(WAVE_EINVAL, "d is NULL with %d receivers", rec->npts);
+        if (!ckpt && grid && grid->ndim == 2 && opts && opts->tile > 0 &&
+            tile_from_id(opts->tile).variant == kTwoStepVariant) {
+            // two steps per pass: the call runs as a batch of one shot
+            wave_shot one;
+            std::memset(&one, 0, sizeof one);
+            one.grid = *grid;
+            one.m = m;
+            one.eta = eta;
+            if (src) one.src = *src;
+            one.q = q;
+            if (rec) one.rec = *rec;
+            one.d = d;
+            one.u_final = u_final;
+            wave_opts o = *opts;
+            o.flags &= ~WAVE_FLAG_PERSISTENT;
+            return wave_forward_batch(1, &one, &o, stream);
+        }
         int rc = setup(C, op, grid, m, eta, src, rec, opts, stream);
         if (rc) return rc;
         CkptView ck;

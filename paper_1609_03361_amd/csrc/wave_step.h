@@ -34,9 +34,6 @@
 #ifndef WAVE_SLAB2_WPE
 #define WAVE_SLAB2_WPE 4
 #endif
-#ifndef WAVE_BATCH2_REMAP
-#define WAVE_BATCH2_REMAP 0
-#endif
 
 namespace wave {
 
@@ -1103,11 +1100,10 @@ __global__ __launch_bounds__(kSlab2Threads, WAVE_SLAB2_WPE) void k_step_batch2(c
     const float* u0 = D.buf[bufs & 3];
     const float* um = D.buf[(bufs >> 2) & 3];
     WAVE_GLOBAL float* d = G(D.d);
-    int64_t lb = b - begin[lo];
-    const int64_t part = a.remap ? (a.stencil_blocks + 7) / 8 * 8 : a.stencil_blocks;
-    if (lb >= part) {
+    const int64_t lb = b - begin[lo];
+    if (lb >= a.stencil_blocks) {
         const int64_t nsb = (a.smp.npts + NT - 1) / NT;
-        const int64_t sb = lb - part;
+        const int64_t sb = lb - a.stencil_blocks;
         const bool second = sb >= nsb;
         const int64_t p = (second ? sb - nsb : sb) * NT + threadIdx.x;
         if (p < a.smp.npts && d) {
@@ -1118,12 +1114,6 @@ __global__ __launch_bounds__(kSlab2Threads, WAVE_SLAB2_WPE) void k_step_batch2(c
         return;
     }
     if (!(flags & 1)) return;
-    if (a.remap) {
-        // shots start at multiples of 8 blocks, so lb & 7 is the XCD: each
-        // XCD takes a contiguous run of tiles (x-neighbours share its L2)
-        lb = (lb & 7) * (part >> 3) + (lb >> 3);
-        if (lb >= a.stencil_blocks) return;
-    }
     a.cur = u0;
     a.other = um;
     a.out = D.buf[(bufs >> 6) & 3];
@@ -1247,11 +1237,11 @@ int64_t plan_t2(StepArgs& a, int xchunk)
     a.xchunk = xchunk;
     const int64_t nchunk = (a.nx + xchunk - 1) / xchunk;
     a.stencil_blocks = (int64_t)a.ntz * nchunk;
-    a.remap = WAVE_BATCH2_REMAP;
-    const int64_t part = a.remap ? (a.stencil_blocks + 7) / 8 * 8 : a.stencil_blocks;
+    // no XCD remap: contiguous runs of columns per XCD measured no faster
+    a.remap = 0;
     int64_t nsb = 0;
     if (a.smp_out && a.smp.npts > 0) nsb = 2 * ((a.smp.npts + kSlab2Threads - 1) / kSlab2Threads);
-    return part + nsb;
+    return a.stencil_blocks + nsb;
 }
 
 // Zero fill (the persistent graph clears its barrier words with it: a kernel

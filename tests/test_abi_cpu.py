@@ -95,9 +95,9 @@ def test_forward_argument_errors_return_before_any_device_work():
     assert _forward_rc(ws=False) == L.WAVE_EWORKSPACE
     assert _forward_rc(ws_bytes=1024) == L.WAVE_EWORKSPACE
     assert b"workspace" in L.lib().wave_last_error()
-    # block shapes: 4 in 2D (ids 0..3), 11 in 3D (ids 0..10)
-    assert _forward_rc(tile=(4 << 16) | 8) == L.WAVE_EINVAL
-    assert b"variant 4" in L.lib().wave_last_error()
+    # block shapes: 4 in 2D (ids 0..3, and 4 = two steps per pass), 11 in 3D (ids 0..10)
+    assert _forward_rc(tile=(5 << 16) | 8) == L.WAVE_EINVAL
+    assert b"variant 5" in L.lib().wave_last_error()
     assert _forward_rc(tile=-1) == L.WAVE_EINVAL
     assert _forward_rc(shape=(20, 30, 40), src=((50.0, 50.0, 50.0),), rec=((10.0, 20.0, 30.0),),
                        tile=(11 << 16) | 8) == L.WAVE_EINVAL
@@ -198,17 +198,32 @@ def test_resolve_tile_clamps_requests():
         api.resolve_tile(geom, 9 << 16)
 
 
-def test_two_step_slab_is_a_batch_only_variant():
-    """2D tile variant 4 (two steps per pass) is offered and accepted for the
-    batched forward only, and a 2D batch workspace holds the second wavefield
-    pair its passes write (3D batches keep one pair)."""
+def test_two_step_variant_scope_and_workspace():
+    """2D tile variant 4 (two steps per pass) is accepted by the batched
+    forward and by the single-shot forward without checkpoints (as a batch of
+    one shot), resolves to columns of 64 rows when planned, and is not among
+    the single-shot tuner's candidates; a 2D batch workspace holds the second
+    wavefield pair its passes write (3D batches keep one pair), and the 2D
+    forward workspace covers the one-shot batch."""
     from paper_1609_03361_amd import api
     geom = api.Geometry((2001, 801), (10.0, 10.0), 8, 1e-3, 10)
     assert all(t >> 16 != 4 for t in api.tile_candidates(geom))
-    with pytest.raises(L.WaveError) as e:
-        api.resolve_tile(geom, 4 << 16)
-    assert e.value.code == L.WAVE_EINVAL
-    assert b"wave_forward_batch only" in L.lib().wave_last_error()
+    assert api.resolve_tile(geom, 4 << 16) == (4 << 16) | 64
+    assert api.resolve_tile(geom, (4 << 16) | 40) == (4 << 16) | 40
+    g = L.make_grid((2001, 801), (10.0, 10.0), 8, 1e-3, 10)
+    sp = L.HostPoints(((5000.0, 25.0),), 2)
+    rp = L.HostPoints(((100.0, 20.0), (200.0, 20.0)), 2)
+    fwd = C.c_size_t(0)
+    assert L.lib().wave_workspace_size(L.WAVE_OP_FORWARD, C.byref(g), C.byref(sp.s), C.byref(rp.s),
+                                       None, C.byref(fwd)) == 0
+    arr = (L.Shot * 1)()
+    arr[0].grid = g
+    arr[0].m = 1 << 20
+    arr[0].src.npts, arr[0].rec.npts = 1, 2
+    arr[0].q, arr[0].d = 1 << 20, 1 << 20
+    one = C.c_size_t(0)
+    assert L.lib().wave_batch_workspace_size(1, arr, None, C.byref(one)) == 0
+    assert fwd.value >= one.value
 
     def batch_bytes(shape):
         arr = (L.Shot * 1)()

@@ -1,5 +1,6 @@
-"""Temporal blocking: the two-step 2D slab (tile variant 4 of the batched
-forward) computes levels n+1 and n+2 in one pass.  Every point's arithmetic
+"""Temporal blocking: the two-step 2D body (tile variant 4 of the batched
+forward and of the single-shot forward without checkpoints) computes levels
+n+1 and n+2 in one pass.  Every point's arithmetic
 is that of a single step, so the traces and final wavefields must equal the
 one-step slab's bit for bit, for even and odd step counts (an odd count
 starts with one step), with and without the graph; and the oracle must agree
@@ -89,13 +90,23 @@ def test_two_step_batched_shots_equal_single_shots_and_oracle(dev):
         assert_close(u[i].cpu().numpy(), ref["u"], f"two-step {probs[i].name} u^nt")
 
 
-def test_two_step_rejected_outside_the_batch(dev):
+def test_two_step_rejected_where_a_step_at_a_time_is_needed(dev):
+    """The checkpointed forward, the adjoint and the gradient take one step
+    per launch: the two-step tile is an argument error there."""
+    import torch
     from paper_1609_03361_amd import api, _lib
     p = synth.random_problem((30, 40), 8, 4, seed=2)
     geom, m, eta, q = device_inputs(p, dev)
-    with pytest.raises(_lib.WaveError) as e:
-        api.forward(geom, m, eta, q, tile=api.tile_id(TWO_STEP, 0))
-    assert e.value.code == _lib.WAVE_EINVAL
+    d = api.forward(geom, m, eta, q)
+    tile = api.tile_id(TWO_STEP, 0)
+    ck = torch.empty(api.checkpoint_bytes(geom, 2), dtype=torch.uint8, device=dev)
+    calls = [lambda: api.forward(geom, m, eta, q, checkpoint=ck, ckpt_every=2, tile=tile),
+             lambda: api.adjoint(geom, m, eta, d, tile=tile),
+             lambda: api.gradient(geom, m, eta, q, d, ckpt_every=2, tile=tile)]
+    for call in calls:
+        with pytest.raises(_lib.WaveError) as e:
+            call()
+        assert e.value.code == _lib.WAVE_EINVAL
 
 
 def test_persistent_batch_maps_the_two_step_tile_to_single_steps(dev):
@@ -125,3 +136,20 @@ def test_tuner_times_the_two_step_slab(dev):
     got = api.forward_batch(shots, return_final=True)
     torch.cuda.synchronize()
     assert _equal(ref[0], got[0]) and _equal(ref[1], got[1])
+
+
+@pytest.mark.parametrize("order,nt,nsrc", [(8, 40, 3), (8, 33, 70), (4, 21, 5), (16, 24, 4)])
+def test_single_shot_forward_two_step_equals_one_step(dev, order, nt, nsrc):
+    """wave_forward without checkpoints on a 2D grid with tile variant 4 runs
+    as a batch of one shot on the two-step body: traces and u^nt bitwise those
+    of the one-step path (70 sources: a dense set, whose one-step run gathers
+    the injection values a step ahead)."""
+    import torch
+    from paper_1609_03361_amd import api
+    p = synth.random_problem((83, 530), order, nt, seed=300 + order + nsrc, nsrc=nsrc, nrec=17)
+    geom, m, eta, q = device_inputs(p, dev)
+    a = api.forward(geom, m, eta, q, return_final=True, tile=api.tile_id(ONE_STEP, 0))
+    for x in (0, 24):
+        b = api.forward(geom, m, eta, q, return_final=True, tile=api.tile_id(TWO_STEP, x))
+        torch.cuda.synchronize()
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), x

@@ -90,11 +90,12 @@ typedef struct {
                                  planned).  Variants (block shapes, z x rows of the (y, z)
                                  plane): 2D 0 = 256 z (4 per lane), 1 = 128 z (1 per lane),
                                  2 = 128 z (2 per lane), 3 = 256 z with x-chunks of at most
-                                 16 rows held in LDS, 4 (wave_forward_batch only, its
-                                 default in 2D) = two time steps per pass over columns of
-                                 x-chunk rows, 64 when planned (temporal blocking,
-                                 256 - 2 ceil4(R) owned z per block, see
-                                 wave_forward_batch); 3D 0 = 64 x 16, 1 = 64 x 8,
+                                 16 rows held in LDS, 4 (wave_forward_batch, where it is
+                                 the 2D default, and wave_forward without checkpoints,
+                                 which then runs as a batch of one shot) = two time
+                                 steps per pass over columns of x-chunk rows, 64 when
+                                 planned (temporal blocking, 256 - 2 ceil4(R) owned z per
+                                 block, see wave_forward_batch); 3D 0 = 64 x 16, 1 = 64 x 8,
                                  2 = 32 x 32, 3 = 100 x 10, 4 = 200 x 5 (4 z-points per
                                  lane), 5 = 64 x 8 (2 per lane), 6 = 64 x 32 (4 per lane),
                                  7 = 64 x 16, 8 = 64 x 32 (2 per lane), 9 = 128 x 16
@@ -148,6 +149,10 @@ int wave_checkpoint_size(const wave_grid* grid, const wave_opts* opts, size_t* b
  *                   and ckpt_dtype (the library cannot check its size):
  *                   receives the snapshots that wave_backward replays
  * Workspace: op WAVE_OP_FORWARD, or WAVE_OP_FORWARD_CKPT when ckpt is given.
+ * In 2D without ckpt, an explicit tile of variant 4 runs the call as a batch
+ * of one shot on the two-step body (wave_forward_batch, whose rules and
+ * errors then apply; the 2D forward workspace covers it).  The result is
+ * bitwise the same.
  */
 int wave_forward(const wave_grid* grid, const float* m, const float* eta,
                  const wave_points* src, const float* q,

@@ -294,8 +294,9 @@ int wave_tune_batch(int32_t nshots, const wave_shot* shots, const wave_opts* opt
                     void* stream, int32_t* tile, double* us_per_step);
 
 /* The tile ids wave_tune times on this grid, in order: every block shape with
- * x-chunks of 2R, 4R, 8, 16, ..., 128 planes, each clamped to what the shape
- * accepts and to the grid, so no two ids launch the same thing.  Writes up
+ * x-chunks of 2R, 4R, 8, 16, ..., 128 planes and of every split of the grid
+ * into 2 .. 32 chunks, each clamped to what the shape accepts and to the
+ * grid, so no two ids launch the same thing.  Writes up
  * to `cap` ids into `ids` and the number of candidates into *n.  Host only. */
 int wave_tile_candidates(const wave_grid* grid, int32_t* ids, int32_t cap, int32_t* n);
 /* The tile a step launch on this grid uses for the requested id (0 = the

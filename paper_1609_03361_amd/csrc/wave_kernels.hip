@@ -217,6 +217,10 @@ __global__ __launch_bounds__(kBlock) void k_sum_half(const float* __restrict__ p
 // the restart velocity carries the relative error of one rounding of d.
 // slot layout per checkpoint: {s_u, s_d, max|u| bits, max|d| bits}.
 // ---------------------------------------------------------------------------
+// FP32 -> BF16 with round to nearest, ties to even, by integer rounding of the
+// bit pattern: add 0x7fff plus the lowest kept bit, then truncate to the upper
+// 16 bits (a carry out of the mantissa moves to the exponent, as rounding up
+// must).  NaN stays a quiet NaN; infinities pass unchanged.
 __device__ __forceinline__ unsigned short f32_to_bf16_rn(float x)
 {
     unsigned int b = __float_as_uint(x);

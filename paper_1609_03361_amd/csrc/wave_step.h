@@ -1014,21 +1014,39 @@ __device__ __forceinline__ void roll2_body(const StepArgs& a, int64_t L, const f
         vstore<VZ>(ring1 + r * P + k * VZ, unload(base1 + r, k));
     }
     const int64_t ulim = X1 + 2 * R;               // u^n rows needed end here
-    // the XR u^n rows from row un: into registers, and from there into the ring
-    auto fetch_u = [&](Vec<VZ>* pv, int64_t un) {
+    // The XR u^n rows of a round: vector m of this thread is row pr[m] of the
+    // round, vector pk[m] of that row.  Its global address advances by XR rows
+    // per round and its ring slot by XR slots, so the loop does no index
+    // arithmetic beyond two additions.
+    const int64_t rlim = ulim < nx ? ulim : nx;    // rows loaded below this, zero above
+    int pr[NPV], pk[NPV], ps[NPV];
+    bool pin[NPV];
+    const float* pp[NPV];
+#pragma unroll
+    for (int m = 0; m < NPV; ++m) {
+        const int i = tid + m * NT;
+        pin[m] = i < XR * NV;
+        const int ii = pin[m] ? i : 0;
+        pr[m] = ii / NV;
+        pk[m] = ii - pr[m] * NV;
+        const int64_t zz = z0 - 2 * RZ + (int64_t)pk[m] * VZ;
+        pin[m] = pin[m] && zz >= 0 && zz < nz;
+        ps[m] = (4 * R + pr[m]) % RING1;           // slot of row X0 + 2R + pr[m] (slot 0: X0 - 2R)
+        pp[m] = a.cur + (X0 + 2 * R + pr[m]) * nz + (pin[m] ? zz : 0);
+    }
+    auto fetch_u = [&](Vec<VZ>* pv, int64_t un) {  // rows un .. un + XR - 1
 #pragma unroll
         for (int m = 0; m < NPV; ++m) {
-            const int i = tid + m * NT;
-            const int r = i / NV, k = i - r * NV;
-            pv[m] = (i < XR * NV && un + r < ulim) ? unload(un + r, k) : vzero<VZ>();
+            pv[m] = (pin[m] && un + pr[m] < rlim) ? vload<VZ>(G(pp[m])) : vzero<VZ>();
+            pp[m] += (int64_t)XR * nz;
         }
     };
-    auto store_u = [&](const Vec<VZ>* pv, int64_t un) {
+    auto store_u = [&](const Vec<VZ>* pv) {        // the round's rows into their slots
 #pragma unroll
         for (int m = 0; m < NPV; ++m) {
-            const int i = tid + m * NT;
-            const int r = i / NV, k = i - r * NV;
-            if (i < XR * NV) vstore<VZ>(row1(un + r) - lane_off + k * VZ, pv[m]);
+            if (tid + m * NT < XR * NV) vstore<VZ>(ring1 + ps[m] * P + pk[m] * VZ, pv[m]);
+            ps[m] += XR;
+            if (ps[m] >= RING1) ps[m] -= RING1;
         }
     };
     int64_t un = X0 + 2 * R;                       // next u^n rows to prefetch
@@ -1052,7 +1070,7 @@ __device__ __forceinline__ void roll2_body(const StepArgs& a, int64_t L, const f
     const int rounds = (int)((X1 - X0 + XR - 1) / XR);      // step-1 rounds; one more for step 2
     for (int j = 0; j <= rounds; ++j) {
         if (j < rounds) {
-            store_u(pv, un);                       // slots of rows no wave reads any more
+            store_u(pv);                           // slots of rows no wave reads any more
             un += XR;
             if (un < ulim) fetch_u(pv, un);
         }

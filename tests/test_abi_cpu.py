@@ -189,6 +189,22 @@ def test_tile_candidates_are_distinct_launches(shape, order):
         assert api.resolve_tile(geom, t) == t
 
 
+def test_tile_candidates_include_every_split_into_2_to_32_chunks():
+    """The tuner's x-chunks include every split of the grid into 2..32 chunks
+    of at least 2R planes (on 200^3 order 8 the best plain step sits at 17
+    planes, between the fixed lengths), besides the fixed lengths 2R, 4R,
+    8 .. 128."""
+    from paper_1609_03361_amd import api
+    geom = api.Geometry((200, 200, 200), (10.0,) * 3, 8, 1e-3, 10)
+    ids = set(api.tile_candidates(geom))
+    for k in range(2, 33):
+        x = -(-200 // k)
+        assert x < 8 or ((3 << 16) | x) in ids, x
+    assert ((3 << 16) | 7) not in ids             # shorter than 2R
+    for x in (8, 16, 32, 64, 128):
+        assert (3 << 16) | x in ids, x
+
+
 def test_resolve_tile_clamps_requests():
     from paper_1609_03361_amd import api
     geom = api.Geometry((2001, 801), (10.0, 10.0), 8, 1e-3, 10)

@@ -23,7 +23,7 @@
 #include "wave_internal.h"
 
 // Build-time knobs of the streaming body (defaults measured best): planes of
-// per-plane operands in flight in 3D, and the largest half-width with the
+// per-plane operands in flight in 3D (two at least), and the largest half-width with the
 // halo lead.
 #ifndef WAVE_PRE_RING_3D
 #define WAVE_PRE_RING_3D 2
@@ -195,6 +195,11 @@ struct Tile {
     // divides S so that the unrolled group of S planes addresses every slot
     // at a compile-time index.
     static constexpr int PR = DIM == 2 ? pre_ring(S, 4) : WAVE_PRE_RING_3D;
+    // a plane's injection range is read (for the early loads of its gathered
+    // values) before that plane's own fetch is issued, so its operands must
+    // come from a fetch at least one plane earlier: a one-slot ring would read
+    // an unfetched range and index the entry arrays with it
+    static_assert(PR >= 2, "the per-plane operand ring needs at least two slots");
     // Halo lead: in 3D, the y/z halo of plane p is loaded together with the
     // queue load of p (R+1 planes before its use) and held in registers, so it
     // is read while the neighbouring tile's load of the same rows is still in

@@ -109,7 +109,11 @@ typedef struct {
 #define WAVE_FLAG_PERSISTENT 2  /* batch: one persistent co-resident launch for all steps (see below) */
 #define WAVE_FLAG_TUNE_IMAGING 4 /* wave_tune (and the workspace size of WAVE_OP_FORWARD): time
                                     the adjoint step with the imaging condition instead of the
-                                    plain step; the result is cached for that kernel only */
+                                    plain step; the result is cached for that kernel only.
+                                    Like the plain tuning it runs without injected or sampled
+                                    points, so a dense receiver set (the gradient's adjoint
+                                    injects every receiver each step) can make its winner
+                                    slower there than the planned tile */
 
 typedef enum {
     WAVE_OP_FORWARD = 0,      /* wave_forward without checkpoints, wave_diffusion, wave_tune */

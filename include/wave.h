@@ -110,10 +110,12 @@ typedef struct {
 #define WAVE_FLAG_TUNE_IMAGING 4 /* wave_tune (and the workspace size of WAVE_OP_FORWARD): time
                                     the adjoint step with the imaging condition instead of the
                                     plain step; the result is cached for that kernel only.
-                                    Like the plain tuning it runs without injected or sampled
-                                    points, so a dense receiver set (the gradient's adjoint
-                                    injects every receiver each step) can make its winner
-                                    slower there than the planned tile */
+                                    wave_tune runs without injected or sampled points, so a
+                                    dense receiver set (the gradient's adjoint injects every
+                                    receiver each step) can make its winner slower there than
+                                    the planned tile; wave_tune_shot times the step with the
+                                    shot's points. wave_tune_shot: the workspace is that of
+                                    WAVE_OP_ADJOINT with this flag, else of WAVE_OP_FORWARD */
 
 typedef enum {
     WAVE_OP_FORWARD = 0,      /* wave_forward without checkpoints, wave_diffusion, wave_tune */
@@ -296,6 +298,24 @@ int wave_tune(const wave_grid* grid, const wave_opts* opts, int32_t steps, void*
               int32_t* tile, double* us_per_step);
 int wave_tune_batch(int32_t nshots, const wave_shot* shots, const wave_opts* opts, int32_t steps,
                     void* stream, int32_t* tile, double* us_per_step);
+/* The same search on one shot's own step: the model m/eta (device, as for
+ * wave_forward) and both point sets (host) are set up as a forward run sets
+ * them up, and every candidate launch injects the sources and samples the
+ * receivers, or with WAVE_FLAG_TUNE_IMAGING runs the adjoint step with the
+ * imaging condition, injecting the receivers and sampling the sources.  The
+ * injected values are zeros and the samples go to a buffer of the tuner's
+ * own (allocated and freed inside the call): the injection and sampling work
+ * is that of a real step, their values do not change a launch's time.
+ * Workspace: op WAVE_OP_FORWARD, or WAVE_OP_ADJOINT with
+ * WAVE_FLAG_TUNE_IMAGING set in opts->flags, sized with the same points.
+ * The winner is cached like wave_tune's; no caller buffer is written.  Like
+ * wave_tune it relaunches the step on the same fields, which stay in the
+ * last-level cache when they fit: its times are then lower than those of a
+ * run that streams other fields between steps (the gradient's replay), and
+ * its ranking of close candidates can differ from theirs. */
+int wave_tune_shot(const wave_grid* grid, const float* m, const float* eta, const wave_points* src,
+                   const wave_points* rec, const wave_opts* opts, int32_t steps, void* stream,
+                   int32_t* tile, double* us_per_step);
 
 /* The tile ids wave_tune times on this grid, in order: every block shape with
  * x-chunks of 2R, 4R, 8, 16, ..., 128 planes and of every split of the grid

@@ -26,7 +26,7 @@ _NAMES = {0: "WAVE_OK", -1: "WAVE_EINVAL", -2: "WAVE_ECFL", -3: "WAVE_ERANGE",
 
 EXPORTS = ["wave_workspace_size", "wave_checkpoint_size", "wave_forward", "wave_adjoint",
            "wave_backward", "wave_gradient", "wave_batch_workspace_size", "wave_forward_batch",
-           "wave_tune", "wave_tune_batch", "wave_last_batch_mode", "wave_diffusion",
+           "wave_tune", "wave_tune_batch", "wave_tune_shot", "wave_last_batch_mode", "wave_diffusion",
            "wave_set_profiling", "wave_last_loop", "wave_misfit", "wave_release",
            "wave_tile_candidates", "wave_resolve_tile", "wave_forward_noalloc",
            "wave_last_error", "wave_version"]
@@ -87,9 +87,11 @@ def lib():
         L.wave_forward_batch.argtypes = [I32, P(Shot), P(Opts), VP]
         L.wave_tune.argtypes = [P(Grid), P(Opts), I32, VP, P(C.c_int32), P(C.c_double)]
         L.wave_tune_batch.argtypes = [I32, P(Shot), P(Opts), I32, VP, P(C.c_int32), P(C.c_double)]
+        L.wave_tune_shot.argtypes = [P(Grid), VP, VP, P(Points), P(Points), P(Opts), I32, VP,
+                                     P(C.c_int32), P(C.c_double)]
         for name in ("wave_workspace_size", "wave_checkpoint_size", "wave_forward", "wave_adjoint",
                      "wave_backward", "wave_gradient", "wave_batch_workspace_size",
-                     "wave_forward_batch", "wave_tune", "wave_tune_batch"):
+                     "wave_forward_batch", "wave_tune", "wave_tune_batch", "wave_tune_shot"):
             getattr(L, name).restype = C.c_int
         L.wave_set_profiling.argtypes = [I32]
         L.wave_set_profiling.restype = C.c_int

@@ -198,10 +198,28 @@ def resolve_tile(geom: Geometry, tile: int = 0) -> int:
     return int(out.value)
 
 
-def tune(geom: Geometry, steps: int = 20, device=None, imaging=False):
+def tune(geom: Geometry, steps: int = 20, device=None, imaging=False, m=None, eta=None):
     """Time every candidate tile on this grid; returns (tile id, us per step).
     The winner is cached for later calls with tile=0; with ``imaging`` the
-    adjoint step with the imaging condition is tuned (and cached) instead."""
+    adjoint step with the imaging condition is tuned (and cached) instead.
+    Given the model ``m`` (and ``eta``), the step is timed as this shot runs
+    it, with its sources and receivers injected and sampled (wave_tune_shot);
+    otherwise on the bare grid (wave_tune)."""
+    if m is not None:
+        _need(m, "m", geom.shape)
+        _need(eta, "eta", geom.shape)
+        dev = m.device
+        grid = geom.grid()
+        sp, rp = geom.points()
+        flags = L.WAVE_FLAG_TUNE_IMAGING if imaging else 0
+        op = L.WAVE_OP_ADJOINT if imaging else L.WAVE_OP_FORWARD
+        ws, o = _workspace(op, grid, sp, rp, dict(flags=flags), dev)
+        t = C.c_int32(0)
+        us = C.c_double(0)
+        L.check(L.lib().wave_tune_shot(C.byref(grid), _ptr(m), _ptr(eta), C.byref(sp.s),
+                                       C.byref(rp.s), C.byref(o), int(steps), _stream(dev),
+                                       C.byref(t), C.byref(us)), "wave_tune_shot")
+        return int(t.value), float(us.value)
     dev = torch.device(device or "cuda:0")
     grid = geom.grid()
     empty = L.HostPoints(None, len(geom.shape))

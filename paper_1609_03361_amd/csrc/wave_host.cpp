@@ -432,8 +432,9 @@ Plan make_plan(int op, const Geo& G, int nsrc, int nrec, const wave_opts* o)
         P.ring = c.take(N * 4 * (size_t)P.nring);
         P.gacc = c.take(N * 4);
     }
-    if (op == WAVE_OP_FORWARD && o && (o->flags & WAVE_FLAG_TUNE_IMAGING)) {
-        // wave_tune of the imaging step: a forward-field plane and a gradient
+    if ((op == WAVE_OP_FORWARD || op == WAVE_OP_ADJOINT) && o && (o->flags & WAVE_FLAG_TUNE_IMAGING)) {
+        // wave_tune (forward plan) or wave_tune_shot (adjoint plan) of the
+        // imaging step: a forward-field plane and a gradient
         P.nring = 1;
         P.ring = c.take(N * 4);
         P.gacc = c.take(N * 4);
@@ -1764,6 +1765,84 @@ int wave_tune(const wave_grid* grid, const wave_opts* opts, int32_t steps, void*
             }
             if (verbose)
                 std::fprintf(stderr, "wave_tune %s: variant %d x-chunk %d: %.2f us\n",
+                             imaging ? "imaging" : "step", cfg.variant, cfg.xchunk, t);
+            if (t < best) { best = t; best_cfg = cfg; }
+        }
+        *tile = tile_id(best_cfg);
+        *us_per_step = best;
+        store_tile(tune_key(C.G, imaging), *tile);
+        return WAVE_OK;
+    } catch (const std::exception& e) {
+        return fail(WAVE_EINVAL, "exception: %s", e.what());
+    } catch (...) {
+        return fail(WAVE_EINVAL, "unknown exception");
+    }
+}
+
+int wave_tune_shot(const wave_grid* grid, const float* m, const float* eta, const wave_points* src,
+                   const wave_points* rec, const wave_opts* opts, int32_t steps, void* stream,
+                   int32_t* tile, double* us_per_step)
+{
+    // zero injection values and a sink for the sampled ones, the tuner's own
+    struct DevBuf {
+        float* p = nullptr;
+        ~DevBuf() { if (p) { (void)hipDeviceSynchronize(); (void)hipFree(p); } }
+    } vals;
+    try {
+        if (!tile || !us_per_step || steps < 1) return fail(WAVE_EINVAL, "tile, us_per_step and steps >= 1 are required");
+        if (!opts) return fail(WAVE_EWORKSPACE, "opts is NULL (it carries the workspace)");
+        const bool imaging = (opts->flags & WAVE_FLAG_TUNE_IMAGING) != 0;
+        Ctx C;
+        int rc = setup(C, imaging ? WAVE_OP_ADJOINT : WAVE_OP_FORWARD, grid, m, eta, src, rec, opts, stream);
+        if (rc) return rc;
+        // the forward injects sources and samples receivers, the imaging
+        // adjoint the other way round
+        const int set = imaging ? 1 : 0;
+        const int ninj = imaging ? C.rec.npts : C.src.npts;
+        const int nsmp = imaging ? C.src.npts : C.rec.npts;
+        const size_t nv = (size_t)ninj + (size_t)nsmp + 1;
+        HIP_TRY(hipMalloc(reinterpret_cast<void**>(&vals.p), nv * sizeof(float)));
+        HIP_TRY(launch_fill(vals.p, (int64_t)nv, 0.f, C.s));
+        const int64_t N = C.G.npad();
+        float* pair[2] = {C.at<float>(imaging ? C.P.adj[0] : C.P.wf[0]),
+                          C.at<float>(imaging ? C.P.adj[1] : C.P.wf[1])};
+        for (float* f : pair) HIP_TRY(launch_fill(f, N, 0.f, C.s));
+        StepArgs a = base_args(C);
+        bind_sparse(C, a, set);
+        a.cur = pair[0];
+        a.other = a.out = pair[1];
+        a.inj_val = ninj ? vals.p : nullptr;
+        a.smp_out = nsmp ? vals.p + ninj : nullptr;
+        if (imaging) {
+            HIP_TRY(launch_fill(C.at<float>(C.P.ring), N, 0.f, C.s));
+            HIP_TRY(launch_fill(C.at<float>(C.P.gacc), N, 0.f, C.s));
+            a.img_fwd = C.at<float>(C.P.ring);
+            a.img_grad = C.at<float>(C.P.gacc);
+        }
+        if (ninj) {
+            HIP_TRY(gather_first(C, a, set, 0, vals.p));
+            gathered(C, a, set, 0, vals.p);
+        }
+        EventPair ev;
+        HIP_TRY(hipEventCreate(&ev.a));
+        HIP_TRY(hipEventCreate(&ev.b));
+        double best = 1e300;
+        TileCfg best_cfg;
+        const bool verbose = std::getenv("WAVE_TUNE_VERBOSE") != nullptr;
+        for (const TileCfg& cfg : tile_candidates(C.G.ndim, C.G.half, C.G.n[0], C.G.nzp)) {
+            for (int w = 0; w < 2; ++w) HIP_TRY(launch_step(C.G.ndim, C.G.order, a, C.s, cfg));
+            double t = 1e300;
+            for (int rep = 0; rep < 3; ++rep) {
+                HIP_TRY(hipEventRecord(ev.a, C.s));
+                for (int i = 0; i < steps; ++i) HIP_TRY(launch_step(C.G.ndim, C.G.order, a, C.s, cfg));
+                HIP_TRY(hipEventRecord(ev.b, C.s));
+                HIP_TRY(hipEventSynchronize(ev.b));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
+                t = std::min(t, 1e3 * ms / steps);
+            }
+            if (verbose)
+                std::fprintf(stderr, "wave_tune_shot %s: variant %d x-chunk %d: %.2f us\n",
                              imaging ? "imaging" : "step", cfg.variant, cfg.xchunk, t);
             if (t < best) { best = t; best_cfg = cfg; }
         }

@@ -170,6 +170,29 @@ def test_imaging_tile_tuned_separately_and_gradient_unchanged(dev):
     assert torch.equal(g0, g1) and torch.equal(J0, J1)
 
 
+def test_tune_shot_times_the_shot_and_results_stay_bitwise(dev):
+    """wave_tune_shot times the step with the shot's own points (forward:
+    sources injected, receivers sampled; imaging adjoint: 300 receivers, a
+    dense set gathered a step ahead, injected and the sources sampled); its
+    winners are cached for tile 0 and change no result."""
+    import torch
+    from paper_1609_03361_amd import api
+    p = synth.random_problem((30, 28, 36), 8, 40, seed=18, nsrc=2, nrec=300)
+    geom, m, eta, q = device_inputs(p, dev)
+    d_obs = api.forward(geom, m * 1.01, eta, q)
+    d0 = api.forward(geom, m, eta, q)
+    J0, g0 = api.gradient(geom, m, eta, q, d_obs, ckpt_every=10)
+    t_f, us_f = api.tune(geom, steps=3, m=m, eta=eta)
+    t_i, us_i = api.tune(geom, steps=3, imaging=True, m=m, eta=eta)
+    print(f"shot-tuned step {t_f >> 16}/{t_f & 0xffff} {us_f:.2f} us; "
+          f"imaging {t_i >> 16}/{t_i & 0xffff} {us_i:.2f} us", flush=True)
+    assert us_f > 0 and us_i > 0
+    d1 = api.forward(geom, m, eta, q)
+    J1, g1 = api.gradient(geom, m, eta, q, d_obs, ckpt_every=10)
+    torch.cuda.synchronize()
+    assert torch.equal(d0, d1) and torch.equal(g0, g1) and torch.equal(J0, J1)
+
+
 def test_dense_sources_gathered_path_equals_direct_bitwise(dev):
     """Point sets of 256 entries or more have their values gathered into entry
     order a step ahead (single-shot launches); the batch kernel reads them
